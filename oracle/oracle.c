@@ -1,0 +1,326 @@
+/*
+ * CPU oracle for brute-force incoherent dedispersion and the boxcar
+ * single-pulse search.  TEST INFRASTRUCTURE ONLY: nothing in the library
+ * links, includes or calls this file; only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark do.
+ *
+ * It is deliberately plain: loops written straight from the definitions,
+ * no blocking, no vectorisation, no shared code with the GPU library.
+ *
+ * Paper: You et al., "A GPU single-pulse search pipeline ..." (arXiv
+ * 2110.12749).  The method is the shift-and-sum of Section 2.3 (Algorithms 2
+ * and 3: each dedispersed sample of a DM trial is the sum over channels of the
+ * channel's sample at the time shifted by that channel's delay), applied per
+ * DM trial of a DDplan-style plan (Section 2.1, Tables 2 and 3: rows of
+ * low DM, DM step, number of DMs and time downsampling).  The paper prints no
+ * dispersion law, no rounding rule and no single-pulse statistic; the
+ * readings taken are:
+ *   delay   d = floor(r + 0.5),  r = ((K * dm) * (1/f^2 - 1/fref^2)) / (tsamp * D)
+ *           K = 4148.808 s MHz^2 cm^3/pc, f in MHz, fref = highest channel,
+ *           evaluated in IEEE double in this order with no FMA contraction;
+ *   downsampling = integer sum of D consecutive samples per channel, the
+ *           remainder dropped;
+ *   valid length n_out = floor(nsamp / D) - max delay over the segment;
+ *   statistics = population mean and sigma from exact integer moments about
+ *           the first sample;
+ *   boxcar  snr(e, w) = (sum_{k=e-w+1..e} x_k - w mu) / (sigma sqrt(w)),
+ *           boxes end-aligned at e, best over widths (ties -> smaller w),
+ *           one candidate per maximal run of best >= threshold at the run's
+ *           argmax (ties -> earlier e).
+ * Parity of the delay table, the downsampled sums, the dedispersed sums, the
+ * statistics and the search is pinned by the CPU tests (exact rationals,
+ * brute force, closed forms, conservation, injected-pulse recovery).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_K_DISP 4148.808
+
+typedef struct {
+  double dm_lo;
+  double dm_step;
+  int32_t n_dm;
+  int32_t downsamp;
+} orc_seg;
+
+typedef struct {
+  int32_t trial;   /* DM index within the segment */
+  int32_t width;   /* boxcar width of the peak, samples */
+  int64_t t_peak;  /* first sample of the peak box */
+  int64_t t_first; /* first box end of the run */
+  int64_t t_last;  /* last box end of the run */
+  double snr;
+} orc_cand;
+
+/* Highest channel frequency: the reference frequency of every delay. */
+double orc_fref(const double *freqs, int32_t nchan) {
+  double f = freqs[0];
+  for (int32_t c = 1; c < nchan; ++c)
+    if (freqs[c] > f) f = freqs[c];
+  return f;
+}
+
+/* Trial DM of index i of a plan row: lo + i * step (half-open grid). */
+double orc_trial_dm(orc_seg s, int32_t i) { return s.dm_lo + (double)i * s.dm_step; }
+
+/* Delay of one channel for one trial, in samples of tsamp * D. */
+int64_t orc_delay(double dm, double f, double fref, double tsamp, int32_t D) {
+  double r = ((ORC_K_DISP * dm) * (1.0 / (f * f) - 1.0 / (fref * fref))) / (tsamp * (double)D);
+  return (int64_t)floor(r + 0.5);
+}
+
+/* Delay table of one segment: int64 [n_dm][nchan]. */
+void orc_delay_table(const double *freqs, int32_t nchan, double tsamp, orc_seg s, int64_t *d) {
+  double fref = orc_fref(freqs, nchan);
+  for (int32_t i = 0; i < s.n_dm; ++i)
+    for (int32_t c = 0; c < nchan; ++c)
+      d[(int64_t)i * nchan + c] = orc_delay(orc_trial_dm(s, i), freqs[c], fref, tsamp, s.downsamp);
+}
+
+/* Per segment: max delay and valid output length (<= 0 means too short). */
+void orc_plan_shape(int64_t nsamp, const double *freqs, int32_t nchan, double tsamp,
+                    const orc_seg *segs, int32_t n_seg, int64_t *max_delay, int64_t *n_out) {
+  double fref = orc_fref(freqs, nchan);
+  for (int32_t s = 0; s < n_seg; ++s) {
+    int64_t m = 0;
+    for (int32_t i = 0; i < segs[s].n_dm; ++i)
+      for (int32_t c = 0; c < nchan; ++c) {
+        int64_t d = orc_delay(orc_trial_dm(segs[s], i), freqs[c], fref, tsamp, segs[s].downsamp);
+        if (d > m) m = d;
+      }
+    max_delay[s] = m;
+    n_out[s] = nsamp / segs[s].downsamp - m;
+  }
+}
+
+/* Y[c][j] = sum_{k<D} X[j*D + k][c]; X time-major uint8 [nsamp][nchan]. */
+void orc_downsample(const uint8_t *X, int64_t nsamp, int32_t nchan, int32_t D, uint32_t *Y) {
+  int64_t N = nsamp / D;
+  for (int32_t c = 0; c < nchan; ++c)
+    for (int64_t j = 0; j < N; ++j) {
+      uint32_t acc = 0;
+      for (int32_t k = 0; k < D; ++k) acc += X[(j * D + k) * nchan + c];
+      Y[(int64_t)c * N + j] = acc;
+    }
+}
+
+/*
+ * Whole segment: out[i][t] = sum_c Y[c][t + d[i][c]], t in [0, n_out).
+ * Trials [i0, i1) only (the full segment when i0 = 0, i1 = n_dm); rows of
+ * `out` are indexed by i - i0.  OpenMP over trials, nothing else.
+ */
+int orc_dedisperse_segment(const uint8_t *X, int64_t nsamp, int32_t nchan, const double *freqs,
+                           double tsamp, orc_seg s, int32_t i0, int32_t i1, int64_t n_out,
+                           int32_t *out) {
+  int64_t N = nsamp / s.downsamp;
+  uint32_t *Y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)N * (size_t)nchan);
+  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)s.n_dm * (size_t)nchan);
+  if (!Y || !d) {
+    free(Y);
+    free(d);
+    return -1;
+  }
+  orc_downsample(X, nsamp, nchan, s.downsamp, Y);
+  orc_delay_table(freqs, nchan, tsamp, s, d);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t i = i0; i < i1; ++i) {
+    int32_t *row = out + (int64_t)(i - i0) * n_out;
+    for (int64_t t = 0; t < n_out; ++t) {
+      int64_t acc = 0;
+      for (int32_t c = 0; c < nchan; ++c) acc += Y[(int64_t)c * N + t + d[(int64_t)i * nchan + c]];
+      row[t] = (int32_t)acc;
+    }
+  }
+  free(Y);
+  free(d);
+  return 0;
+}
+
+/*
+ * Individual outputs straight from the raw filterbank, no intermediate
+ * arrays: value[k] = sum_c sum_{m<D} X[(t_k + d(i_k, c)) * D + m][c].
+ */
+void orc_dedisperse_points(const uint8_t *X, int64_t nsamp, int32_t nchan, const double *freqs,
+                           double tsamp, orc_seg s, const int32_t *trial, const int64_t *t,
+                           int64_t npts, int64_t *value) {
+  double fref = orc_fref(freqs, nchan);
+  (void)nsamp;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < npts; ++k) {
+    double dm = orc_trial_dm(s, trial[k]);
+    int64_t acc = 0;
+    for (int32_t c = 0; c < nchan; ++c) {
+      int64_t d = orc_delay(dm, freqs[c], fref, tsamp, s.downsamp);
+      for (int32_t m = 0; m < s.downsamp; ++m) acc += X[((t[k] + d) * s.downsamp + m) * nchan + c];
+    }
+    value[k] = acc;
+  }
+}
+
+/*
+ * Population mean and sigma of x[0..n), from exact moments about x0 = x[0]:
+ * S1 = sum (x - x0), S2 = sum (x - x0)^2 in 128-bit integers, then
+ * mu = x0 + S1/n and sigma = sqrt(S2/n - (S1/n)^2) in double.
+ */
+void orc_stats(const int32_t *x, int64_t n, double *mu, double *sigma) {
+  __int128 s1 = 0, s2 = 0;
+  int64_t x0 = x[0];
+  for (int64_t k = 0; k < n; ++k) {
+    __int128 v = (__int128)((int64_t)x[k] - x0);
+    s1 += v;
+    s2 += v * v;
+  }
+  double m1 = (double)s1 / (double)n;
+  double m2 = (double)s2 / (double)n;
+  double var = m2 - m1 * m1;
+  *mu = (double)x0 + m1;
+  *sigma = var > 0.0 ? sqrt(var) : 0.0;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Boxcar search of the box ends e in [e0, e1) of series x[0..n), with the
+ * statistics mu, sigma given.  Boxes may start anywhere >= 0 (they reach back
+ * before e0 when e0 > 0).  Candidates are appended to out (capacity cap);
+ * returns the number found (may exceed cap; only cap are written).
+ */
+int64_t orc_search_range(const int32_t *x, int64_t n, int64_t e0, int64_t e1, double mu, double sigma,
+                         const int32_t *widths_in, int32_t nw, float threshold, int32_t trial,
+                         orc_cand *out, int64_t cap) {
+  if (e0 < 0) e0 = 0;
+  if (e1 > n) e1 = n;
+  if (!(sigma > 0.0) || e1 <= e0 || nw <= 0) return 0;
+  /* widths as a sorted set */
+  int32_t *w = (int32_t *)malloc(sizeof(int32_t) * (size_t)nw);
+  memcpy(w, widths_in, sizeof(int32_t) * (size_t)nw);
+  qsort(w, (size_t)nw, sizeof(int32_t), cmp_i32);
+  int32_t nu = 0;
+  for (int32_t k = 0; k < nw; ++k)
+    if (nu == 0 || w[k] != w[nu - 1]) w[nu++] = w[k];
+  /* prefix sums P[k] = x[0] + ... + x[k-1] */
+  int64_t *P = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  P[0] = 0;
+  for (int64_t k = 0; k < n; ++k) P[k + 1] = P[k] + (int64_t)x[k];
+  double thr = (double)threshold;
+  int64_t found = 0;
+  int in_run = 0;
+  int64_t run_first = 0, best_e = 0;
+  int32_t best_w = 0;
+  double best_snr = 0.0;
+  for (int64_t e = e0; e <= e1; ++e) {
+    int flagged = 0;
+    double b = 0.0;
+    int32_t bw = 0;
+    if (e < e1) {
+      for (int32_t k = 0; k < nu; ++k) {
+        int64_t wk = w[k];
+        if (wk > e + 1) break; /* box would start before sample 0 */
+        double s = (double)(P[e + 1] - P[e + 1 - wk]);
+        double snr = (s - (double)wk * mu) / (sigma * sqrt((double)wk));
+        if (bw == 0 || snr > b) {
+          b = snr;
+          bw = (int32_t)wk;
+        }
+      }
+      flagged = bw != 0 && b >= thr;
+    }
+    if (flagged) {
+      if (!in_run) {
+        in_run = 1;
+        run_first = e;
+        best_e = e;
+        best_w = bw;
+        best_snr = b;
+      } else if (b > best_snr) {
+        best_e = e;
+        best_w = bw;
+        best_snr = b;
+      }
+    } else if (in_run) {
+      if (found < cap) {
+        orc_cand *c = &out[found];
+        c->trial = trial;
+        c->width = best_w;
+        c->t_peak = best_e - best_w + 1;
+        c->t_first = run_first;
+        c->t_last = e - 1;
+        c->snr = best_snr;
+      }
+      ++found;
+      in_run = 0;
+    }
+  }
+  free(P);
+  free(w);
+  return found;
+}
+
+/* Whole-series search: statistics over all n samples, every box end. */
+int64_t orc_search_series(const int32_t *x, int64_t n, const int32_t *widths, int32_t nw,
+                          float threshold, int32_t trial, orc_cand *out, int64_t cap) {
+  double mu, sigma;
+  if (n <= 0) return 0;
+  orc_stats(x, n, &mu, &sigma);
+  return orc_search_range(x, n, 0, n, mu, sigma, widths, nw, threshold, trial, out, cap);
+}
+
+/*
+ * Streaming window search: statistics over the window's own samples
+ * x[w0..w1) and boxes ending in it, which may reach back before w0.
+ */
+int64_t orc_search_window(const int32_t *x, int64_t n, int64_t w0, int64_t w1, const int32_t *widths,
+                          int32_t nw, float threshold, int32_t trial, orc_cand *out, int64_t cap) {
+  double mu, sigma;
+  if (w0 < 0) w0 = 0;
+  if (w1 > n) w1 = n;
+  if (w1 <= w0) return 0;
+  orc_stats(x + w0, w1 - w0, &mu, &sigma);
+  return orc_search_range(x, n, w0, w1, mu, sigma, widths, nw, threshold, trial, out, cap);
+}
+
+/*
+ * Friends-of-friends grouping of candidates of one segment.  Two candidates
+ * are linked when their trial indices differ by at most one and their run
+ * extents [t_first, t_last] overlap.  group[k] receives, for candidate k, the
+ * index of its group's representative: the member of highest snr (ties ->
+ * lower trial, then earlier t_peak).  Quadratic on purpose.
+ */
+void orc_group(const orc_cand *c, int64_t n, int64_t *group) {
+  int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  for (int64_t k = 0; k < n; ++k) parent[k] = k;
+  for (int64_t a = 0; a < n; ++a)
+    for (int64_t b = a + 1; b < n; ++b) {
+      int64_t dt = (int64_t)c[a].trial - (int64_t)c[b].trial;
+      if (dt < -1 || dt > 1) continue;
+      if (c[a].t_last < c[b].t_first || c[b].t_last < c[a].t_first) continue;
+      int64_t ra = a, rb = b;
+      while (parent[ra] != ra) ra = parent[ra];
+      while (parent[rb] != rb) rb = parent[rb];
+      if (ra != rb) parent[ra > rb ? ra : rb] = ra < rb ? ra : rb;
+    }
+  /* representative = best member of each root's set */
+  int64_t *best = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  for (int64_t k = 0; k < n; ++k) best[k] = -1;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t r = k;
+    while (parent[r] != r) r = parent[r];
+    int64_t b = best[r];
+    int better = b < 0 || c[k].snr > c[b].snr ||
+                 (c[k].snr == c[b].snr &&
+                  (c[k].trial < c[b].trial || (c[k].trial == c[b].trial && c[k].t_peak < c[b].t_peak)));
+    if (better) best[r] = k;
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t r = k;
+    while (parent[r] != r) r = parent[r];
+    group[k] = best[r];
+  }
+  free(best);
+  free(parent);
+}
