@@ -57,6 +57,8 @@ def lib():
             build()
         L = C.CDLL(LIB)
         P = C.c_void_p
+        L.orc_num_threads.restype = C.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_fref.restype = C.c_double
         L.orc_fref.argtypes = [P, C.c_int32]
         L.orc_trial_dm.restype = C.c_double
@@ -98,6 +100,10 @@ def _ptr(a: np.ndarray):
 def _seg(s) -> Seg:
     dm_lo, dm_step, n_dm, d = s
     return Seg(float(dm_lo), float(dm_step), int(n_dm), int(d))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def fref(freqs) -> float:

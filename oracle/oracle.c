@@ -35,8 +35,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_K_DISP 4148.808
+
+/* Threads an OpenMP loop of the oracle uses (reported with CPU timings). */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 typedef struct {
   double dm_lo;
@@ -107,33 +111,34 @@ void orc_downsample(const uint8_t *X, int64_t nsamp, int32_t nchan, int32_t D, u
 }
 
 /*
- * Whole segment: out[i][t] = sum_c Y[c][t + d[i][c]], t in [0, n_out).
- * Trials [i0, i1) only (the full segment when i0 = 0, i1 = n_dm); rows of
- * `out` are indexed by i - i0.  OpenMP over trials, nothing else.
+ * Whole segment: out[i][t] = sum_c Y[c][t + d[i][c]], t in [0, n_out), with
+ * Y[c][j] = sum_{m<D} X[j*D + m][c] evaluated on the fly from the raw
+ * filterbank (no intermediate array).  Trials [i0, i1) only (the full
+ * segment when i0 = 0, i1 = n_dm); rows of `out` are indexed by i - i0.
+ * OpenMP over the (trial, sample) pairs, nothing else.
  */
 int orc_dedisperse_segment(const uint8_t *X, int64_t nsamp, int32_t nchan, const double *freqs,
                            double tsamp, orc_seg s, int32_t i0, int32_t i1, int64_t n_out,
                            int32_t *out) {
-  int64_t N = nsamp / s.downsamp;
-  uint32_t *Y = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)N * (size_t)nchan);
-  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)s.n_dm * (size_t)nchan);
-  if (!Y || !d) {
-    free(Y);
-    free(d);
-    return -1;
-  }
-  orc_downsample(X, nsamp, nchan, s.downsamp, Y);
-  orc_delay_table(freqs, nchan, tsamp, s, d);
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int32_t i = i0; i < i1; ++i) {
-    int32_t *row = out + (int64_t)(i - i0) * n_out;
+  (void)nsamp;
+  int32_t nt = i1 - i0;
+  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1) * (size_t)nchan);
+  if (!d) return -1;
+  double fref = orc_fref(freqs, nchan);
+  for (int32_t i = i0; i < i1; ++i)
+    for (int32_t c = 0; c < nchan; ++c)
+      d[(int64_t)(i - i0) * nchan + c] = orc_delay(orc_trial_dm(s, i), freqs[c], fref, tsamp, s.downsamp);
+  const int64_t D = s.downsamp;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int32_t i = 0; i < nt; ++i)
     for (int64_t t = 0; t < n_out; ++t) {
       int64_t acc = 0;
-      for (int32_t c = 0; c < nchan; ++c) acc += Y[(int64_t)c * N + t + d[(int64_t)i * nchan + c]];
-      row[t] = (int32_t)acc;
+      for (int32_t c = 0; c < nchan; ++c) {
+        int64_t j = t + d[(int64_t)i * nchan + c];
+        for (int64_t m = 0; m < D; ++m) acc += X[(j * D + m) * nchan + c];
+      }
+      out[(int64_t)i * n_out + t] = (int32_t)acc;
     }
-  }
-  free(Y);
   free(d);
   return 0;
 }

@@ -1,0 +1,142 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gsp.h"
+
+namespace gsp {
+
+// Error carried from deep inside the runtime to the ABI boundary.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+// Device buffer owned by the library (grow-only).
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int device = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  void reserve(size_t n);  // grow to at least n bytes; contents not preserved
+  template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Launch shape of the dedispersion kernel for one plan row.
+struct DedispShape {
+  int tpw = 4;       // trials per wave
+  int waves = 8;     // waves per block
+  int groups = 8;    // dword groups per lane (samples per block = 128 * groups)
+  int chunk = 32;    // channels staged per pass
+  int trials_per_block() const { return tpw * waves; }
+  int samples_per_block() const { return 128 * groups; }
+};
+
+// Per-row device tables for one plan (cached by plan key).
+struct RowTables {
+  int32_t n_dm = 0, D = 1, nchan = 0;
+  int64_t N = 0;         // downsampled length
+  int64_t n_out = 0;
+  int64_t max_delay = 0;
+  DedispShape shape;
+  int64_t lds_bytes = 0;     // dynamic LDS per block
+  int32_t row_dwords = 0;    // LDS dwords per staged copy of a channel
+  DevBuf addr;               // uint32 [n_dm_pad][nchan]: LDS dword offset per (trial, channel)
+  DevBuf dmin;               // int32 [n_tiles][nchan]: aligned first delay per DM tile
+  std::vector<int32_t> delays_host;  // int32 [n_dm][nchan]
+};
+
+// One timed kernel launch (profiling enabled).
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+  double work;
+};
+
+struct PlanCache {
+  std::string key;
+  std::vector<std::unique_ptr<RowTables>> rows;
+};
+
+}  // namespace gsp
+
+struct gsp_ctx {
+  int device = 0;
+  std::string last_error;
+  std::map<std::string, std::unique_ptr<gsp::PlanCache>> plans;
+  gsp::DevBuf staged;      // channel-major downsampled input of the current row
+  gsp::DevBuf stats;       // per-trial moments / mu / sigma
+  gsp::DevBuf frags;       // search run fragments
+  gsp::DevBuf counter;     // fragment counter
+  gsp::DevBuf widths;      // device copy of the width set
+  std::vector<uint8_t> host_scratch;
+  // tuned shapes keyed by row signature
+  std::map<std::string, gsp::DedispShape> tuned;
+  // profiling
+  bool prof = false;
+  std::vector<gsp::ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+};
+
+namespace gsp {
+
+// Profiling brackets around a kernel launch (no-ops when disabled).
+struct ProfScope {
+  gsp_ctx *ctx;
+  hipStream_t st;
+  size_t idx;
+  ProfScope(gsp_ctx *c, const char *name, hipStream_t s, double work);
+  ~ProfScope();
+};
+
+// Plan helpers (plan.cpp)
+double fref_of(const double *freqs, int32_t nchan);
+int64_t delay_of(double dm, double f, double fref, double tsamp, int32_t D);
+void validate_desc(const gsp_dmt_desc *desc);
+void plan_shape_impl(int64_t nsamp, int32_t nchan, const double *freqs, double tsamp, const gsp_segment *segs,
+                     int32_t n_seg, gsp_dmt_desc *desc);
+void compute_delays(const gsp_dmt_desc *desc, const double *freqs, int32_t s, int32_t *out);
+std::string plan_key(const gsp_dmt_desc *desc, const double *freqs);
+
+// Dedispersion (dedisp.hip)
+DedispShape default_shape(int32_t D);
+void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
+                      const DedispShape &shape, RowTables &rt);
+void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st);
+void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
+int64_t staged_pitch(const RowTables &rt);
+
+// Search (search.hip)
+struct Frag {  // one run of flagged box ends inside a search tile
+  int32_t trial;    // global trial index
+  int32_t width;    // peak width
+  int64_t t_first;  // first box end
+  int64_t t_last;   // last box end
+  int64_t e_peak;   // box end of the peak
+  double snr;
+  int32_t open_left;   // run starts at the tile's first box end (tile > 0)
+  int32_t open_right;  // run ends at the tile's last box end (not the series end)
+};
+static_assert(sizeof(Frag) == 48, "fragment layout");
+
+void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
+// Device pointer of per-trial mu/sigma (double[2*n_trials]) after launch_stats.
+const double *stats_musig(gsp_ctx *ctx, const gsp_dmt_desc *desc);
+void launch_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, const int32_t *widths_dev,
+                   int32_t n_widths, int32_t max_width, float thr, Frag *frags, int64_t cap,
+                   unsigned long long *counter, hipStream_t st);
+
+}  // namespace gsp

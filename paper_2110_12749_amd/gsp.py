@@ -1,0 +1,239 @@
+"""Python binding of libgsp.so (include/gsp.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; torch supplies
+device memory and streams.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsp.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+_L = C.CDLL(LIB_PATH)
+
+GSP_OK, GSP_EINVAL, GSP_ETOOSHORT, GSP_EOVERFLOW, GSP_ECAPACITY, GSP_ENOMEM, GSP_EDEVICE, GSP_EAGAIN = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MAX_SEG = 16
+
+
+class Segment(C.Structure):
+    _fields_ = [("dm_lo", C.c_double), ("dm_step", C.c_double), ("n_dm", C.c_int32), ("downsamp", C.c_int32)]
+
+
+class DmtDesc(C.Structure):
+    _fields_ = [("nsamp", C.c_int64), ("nchan", C.c_int32), ("n_seg", C.c_int32), ("tsamp", C.c_double),
+                ("fref_mhz", C.c_double), ("seg", Segment * MAX_SEG), ("max_delay", C.c_int64 * MAX_SEG),
+                ("n_out", C.c_int64 * MAX_SEG), ("offset", C.c_int64 * MAX_SEG), ("trial0", C.c_int32 * MAX_SEG),
+                ("n_trials", C.c_int32), ("pad_", C.c_int32), ("total", C.c_int64)]
+
+
+class Candidate(C.Structure):
+    _fields_ = [("seg", C.c_int32), ("dm_index", C.c_int32), ("dm", C.c_double), ("t_peak", C.c_int64),
+                ("t_first", C.c_int64), ("t_last", C.c_int64), ("width", C.c_int32), ("snr", C.c_float),
+                ("time_s", C.c_double)]
+
+
+CAND_DTYPE = np.dtype([("seg", np.int32), ("dm_index", np.int32), ("dm", np.float64), ("t_peak", np.int64),
+                       ("t_first", np.int64), ("t_last", np.int64), ("width", np.int32), ("snr", np.float32),
+                       ("time_s", np.float64)])
+assert CAND_DTYPE.itemsize == C.sizeof(Candidate)
+
+P = C.c_void_p
+_L.gsp_create.restype = C.c_int
+_L.gsp_create.argtypes = [C.c_int, C.POINTER(P)]
+_L.gsp_destroy.restype = None
+_L.gsp_destroy.argtypes = [P]
+_L.gsp_strerror.restype = C.c_char_p
+_L.gsp_strerror.argtypes = [C.c_int]
+_L.gsp_last_error.restype = C.c_char_p
+_L.gsp_last_error.argtypes = [P]
+_L.gsp_plan_shape.restype = C.c_int
+_L.gsp_plan_shape.argtypes = [C.c_int64, C.c_int32, P, C.c_double, P, C.c_int32, C.POINTER(DmtDesc)]
+_L.gsp_delay_table.restype = C.c_int
+_L.gsp_delay_table.argtypes = [C.POINTER(DmtDesc), P, C.c_int32, P]
+_L.gsp_dedisperse.restype = C.c_int
+_L.gsp_dedisperse.argtypes = [P, P, P, C.POINTER(DmtDesc), P, P]
+_L.gsp_trial_stats.restype = C.c_int
+_L.gsp_trial_stats.argtypes = [P, P, C.POINTER(DmtDesc), P, P, P]
+_L.gsp_single_pulse_search.restype = C.c_int
+_L.gsp_single_pulse_search.argtypes = [P, P, C.POINTER(DmtDesc), P, C.c_int32, C.c_float, P, C.c_int64,
+                                       C.POINTER(C.c_int64), P]
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("work", C.c_double)]
+
+
+_L.gsp_profile_enable.restype = C.c_int
+_L.gsp_profile_enable.argtypes = [P, C.c_int]
+_L.gsp_profile_read.restype = C.c_int
+_L.gsp_profile_read.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.c_int]
+_L.gsp_group_candidates.restype = C.c_int
+_L.gsp_group_candidates.argtypes = [P, C.c_int64, P, C.POINTER(C.c_int64)]
+
+
+class GspError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        text = _L.gsp_strerror(status).decode()
+        super().__init__(f"{text} ({status})" + (f": {msg}" if msg else ""))
+
+
+def lib():
+    return _L
+
+
+def _check(status: int, ctx=None):
+    if status != GSP_OK:
+        msg = _L.gsp_last_error(ctx).decode() if ctx else ""
+        raise GspError(status, msg)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _segs(segments):
+    arr = (Segment * len(segments))()
+    for k, (lo, st, n, d) in enumerate(segments):
+        arr[k] = Segment(float(lo), float(st), int(n), int(d))
+    return arr
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def plan_shape(nsamp: int, freqs, tsamp: float, segments) -> DmtDesc:
+    """Validate a plan and return its output descriptor (gsp_plan_shape)."""
+    f = _f64(freqs)
+    d = DmtDesc()
+    segs = _segs(segments)
+    _check(_L.gsp_plan_shape(int(nsamp), len(f), f.ctypes.data, float(tsamp), C.addressof(segs), len(segments),
+                             C.byref(d)))
+    return d
+
+
+def delay_table(desc: DmtDesc, freqs, seg: int) -> np.ndarray:
+    f = _f64(freqs)
+    out = np.empty((desc.seg[seg].n_dm, desc.nchan), np.int32)
+    _check(_L.gsp_delay_table(C.byref(desc), f.ctypes.data, int(seg), out.ctypes.data))
+    return out
+
+
+def segment_views(desc: DmtDesc, dmt):
+    """Per-row [n_dm][n_out] views of a flat DM-time array."""
+    return [dmt[desc.offset[s]: desc.offset[s] + desc.seg[s].n_dm * desc.n_out[s]].view(desc.seg[s].n_dm,
+                                                                                         desc.n_out[s])
+            for s in range(desc.n_seg)]
+
+
+def group_candidates(cands: np.ndarray):
+    """(representative index per candidate, number of groups)."""
+    c = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    rep = np.empty(len(c), np.int64)
+    ng = C.c_int64()
+    _check(_L.gsp_group_candidates(c.ctypes.data, len(c), rep.ctypes.data, C.byref(ng)))
+    return rep, int(ng.value)
+
+
+class Context:
+    """A library context (gsp_create) bound to one device."""
+
+    def __init__(self, device: int = 0):
+        h = P()
+        _check(_L.gsp_create(int(device), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.gsp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile_enable(self, on: bool = True):
+        _check(_L.gsp_profile_enable(self.h, int(bool(on))), self.h)
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{kernel name: (launches, total_ms, work)} of the timed launches."""
+        cap = 32
+        arr = (KernelStat * cap)()
+        n = C.c_int32()
+        _check(_L.gsp_profile_read(self.h, C.addressof(arr), cap, C.byref(n), int(bool(reset))), self.h)
+        return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms), float(arr[k].work))
+                for k in range(min(n.value, cap))}
+
+    def dedisperse(self, fb, freqs, desc: DmtDesc, out=None, stream=None):
+        """fb: torch uint8 [nsamp][nchan] on the device.  Returns int32 [total]."""
+        import torch
+        assert fb.dtype == torch.uint8 and fb.is_cuda and fb.is_contiguous()
+        assert tuple(fb.shape) == (desc.nsamp, desc.nchan)
+        if out is None:
+            out = torch.empty(desc.total, dtype=torch.int32, device=fb.device)
+        assert out.dtype == torch.int32 and out.is_contiguous() and out.numel() >= desc.total
+        f = _f64(freqs)
+        _check(_L.gsp_dedisperse(self.h, C.c_void_p(fb.data_ptr()), f.ctypes.data, C.byref(desc),
+                                 C.c_void_p(out.data_ptr()), _stream_handle(stream)), self.h)
+        return out
+
+    def trial_stats(self, dmt, desc: DmtDesc, stream=None):
+        mu = np.empty(desc.n_trials, np.float64)
+        sg = np.empty(desc.n_trials, np.float64)
+        _check(_L.gsp_trial_stats(self.h, C.c_void_p(dmt.data_ptr()), C.byref(desc), mu.ctypes.data, sg.ctypes.data,
+                                  _stream_handle(stream)), self.h)
+        return mu, sg
+
+    def single_pulse_search(self, dmt, desc: DmtDesc, widths, threshold: float, capacity: int = 1 << 16,
+                            stream=None) -> np.ndarray:
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        while True:
+            out = np.zeros(capacity, CAND_DTYPE)
+            n = C.c_int64()
+            st = _L.gsp_single_pulse_search(self.h, C.c_void_p(dmt.data_ptr()), C.byref(desc), w.ctypes.data, len(w),
+                                            float(threshold), out.ctypes.data, capacity, C.byref(n),
+                                            _stream_handle(stream))
+            if st == GSP_ECAPACITY:
+                capacity = int(n.value)
+                continue
+            _check(st, self.h)
+            return out[: n.value]
+
+
+_default = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def dedisperse(fb, freqs, tsamp: float, segments, ctx: Context | None = None, stream=None):
+    """dedisperse(filterbank, freqs, tsamp, dm_plan) -> (int32 DM-time array, descriptor)."""
+    desc = plan_shape(fb.shape[0], freqs, tsamp, segments)
+    ctx = ctx or context(fb.device.index or 0)
+    return ctx.dedisperse(fb, freqs, desc, stream=stream), desc
+
+
+def single_pulse_search(dmt, desc: DmtDesc, widths, threshold: float, ctx: Context | None = None, stream=None):
+    """single_pulse_search(dmt, widths, threshold) -> candidate array (CAND_DTYPE)."""
+    ctx = ctx or context(dmt.device.index or 0)
+    return ctx.single_pulse_search(dmt, desc, widths, threshold, stream=stream)
+
+
+def trial_stats(dmt, desc: DmtDesc, ctx: Context | None = None, stream=None):
+    ctx = ctx or context(dmt.device.index or 0)
+    return ctx.trial_stats(dmt, desc, stream=stream)
