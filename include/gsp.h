@@ -133,7 +133,8 @@ typedef struct gsp_candidate {
 
 /* Boxcar matched-filter search of a dedispersed plan.
  * For every trial: mu, sigma as in gsp_trial_stats; for every width w of the
- * set `widths` (host int32[n_widths], each >= 1, duplicates ignored) and box
+ * set `widths` (host int32[n_widths], n_widths <= 64, each in [1, 4096],
+ * duplicates ignored) and box
  * end e with w-1 <= e < n_out:  snr(e,w) = (sum_{k=e-w+1..e} x_k - w*mu) /
  * (sigma*sqrt(w)) in double; best(e) = max over w (ties -> smaller w); each
  * maximal run of e with best(e) >= threshold gives one candidate at its
@@ -152,6 +153,35 @@ int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt_dev, const gsp_dmt_
  * the representative of k's group: the member of highest snr (ties -> lower
  * dm_index, then earlier t_peak).  Returns the number of groups via n_groups. */
 int gsp_group_candidates(const gsp_candidate *cands, int64_t n, int64_t *rep_out, int64_t *n_groups);
+
+/* Launch shape of the dedispersion kernel for one plan row: each workgroup
+ * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials
+ * over 128*`groups` output samples; `chunk` channels are staged into LDS per
+ * pass (the library lowers it to fit LDS and its staging registers). */
+typedef struct gsp_shape {
+  int32_t groups; /* 2, 4 or 8 */
+  int32_t tpw;    /* 4 or 8 */
+  int32_t waves;  /* 1 .. 8 */
+  int32_t chunk;  /* >= 1 */
+} gsp_shape;
+
+/* Autotuner.  For every plan row of `desc`, times the dedispersion kernel
+ * with each built-in candidate shape on the given input (dmt_dev is
+ * overwritten; fb_dev as in gsp_dedisperse), `n_reps` timed launches each,
+ * keeps the fastest and uses it for every later call on this context whose
+ * row has the same signature (nchan, D, n_dm, maximum delay, length class).
+ * Synchronises `stream`. */
+int gsp_autotune(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const gsp_dmt_desc *desc,
+                 int32_t *dmt_dev, int32_t n_reps, void *stream);
+/* The shape in use (or that would be used) for row `seg` of a plan. */
+int gsp_row_shape(gsp_ctx *ctx, const double *freqs_mhz, const gsp_dmt_desc *desc, int32_t seg, gsp_shape *out);
+/* Force a shape for rows with the signature of row `seg` (tests, tuning). */
+int gsp_set_row_shape(gsp_ctx *ctx, const double *freqs_mhz, const gsp_dmt_desc *desc, int32_t seg,
+                      const gsp_shape *shape);
+/* Tuned shapes as text, one "signature groups tpw waves chunk" line per row
+ * signature; load merges into the context's table. */
+int gsp_tuning_save(const gsp_ctx *ctx, const char *path);
+int gsp_tuning_load(gsp_ctx *ctx, const char *path);
 
 /* Kernel timing (tracing).  When enabled, the library brackets each of its
  * kernel launches with a pair of HIP events on the launch's stream.

@@ -58,7 +58,7 @@ ProfScope::~ProfScope() {
   if (idx != SIZE_MAX) (void)hipEventRecord(ctx->prof_recs[idx].stop, st);
 }
 
-static RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s) {
+RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s) {
   const std::string key = plan_key(desc, freqs);
   auto it = ctx->plans.find(key);
   if (it == ctx->plans.end()) {
@@ -69,10 +69,15 @@ static RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const doubl
     it = ctx->plans.emplace(key, std::move(pc)).first;
   }
   auto &slot = it->second->rows[s];
+  const DedispShape want = shape_for_row(ctx, desc, s);
+  if (slot && (slot->shape.groups != want.groups || slot->shape.tpw != want.tpw || slot->shape.waves != want.waves ||
+               slot->req_chunk != want.chunk))
+    slot.reset();  // the tuned shape changed since the tables were built
   if (!slot) {
-    slot = std::make_unique<RowTables>();
-    DedispShape sh = default_shape(desc->seg[s].downsamp);
-    build_row_tables(ctx, desc, freqs, s, sh, *slot);
+    auto rt = std::make_unique<RowTables>();
+    build_row_tables(ctx, desc, freqs, s, want, *rt);
+    rt->req_chunk = want.chunk;
+    slot = std::move(rt);
   }
   return *slot;
 }
@@ -81,25 +86,6 @@ static RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const doubl
 
 using namespace gsp;
 
-
-template <class F>
-static int guarded(gsp_ctx *ctx, F &&f) {
-  try {
-    if (ctx) check_hip(hipSetDevice(ctx->device), "select device");
-    f();
-    if (ctx) ctx->last_error.clear();
-    return GSP_OK;
-  } catch (const Error &e) {
-    if (ctx) ctx->last_error = e.msg;
-    return e.status;
-  } catch (const std::bad_alloc &) {
-    if (ctx) ctx->last_error = "host allocation failed";
-    return GSP_ENOMEM;
-  } catch (...) {
-    if (ctx) ctx->last_error = "unexpected internal error";
-    return GSP_EDEVICE;
-  }
-}
 
 extern "C" {
 
@@ -252,7 +238,7 @@ int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc
     if (!std::isfinite(threshold)) fail(GSP_EINVAL, "threshold must be finite");
     std::vector<int32_t> w(widths, widths + n_widths);
     for (int32_t v : w)
-      if (v < 1 || v > 8192) fail(GSP_EINVAL, "widths must be in [1, 8192]");
+      if (v < 1 || v > 4096) fail(GSP_EINVAL, "widths must be in [1, 4096]");
     std::sort(w.begin(), w.end());
     w.erase(std::unique(w.begin(), w.end()), w.end());
     hipStream_t st = static_cast<hipStream_t>(stream);

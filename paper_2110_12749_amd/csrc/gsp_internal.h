@@ -52,6 +52,7 @@ struct RowTables {
   int64_t n_out = 0;
   int64_t max_delay = 0;
   DedispShape shape;
+  int32_t req_chunk = 0;     // chunk requested by the shape (before LDS limits)
   int64_t lds_bytes = 0;     // dynamic LDS per block
   int32_t row_dwords = 0;    // LDS dwords per staged copy of a channel
   DevBuf addr;               // uint32 [n_dm_pad][nchan]: LDS dword offset per (trial, channel)
@@ -71,6 +72,15 @@ struct PlanCache {
   std::vector<std::unique_ptr<RowTables>> rows;
 };
 
+}  // namespace gsp
+
+struct gsp_ctx;
+
+namespace gsp {
+// Run f at the ABI boundary: select the context's device, turn every error
+// into a status code and keep its message on the context.
+template <class F>
+int guarded(gsp_ctx *ctx, F &&f);
 }  // namespace gsp
 
 struct gsp_ctx {
@@ -102,6 +112,9 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Cached device tables of row s of a plan, built for the row's current shape (api.cpp)
+RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s);
+
 // Plan helpers (plan.cpp)
 double fref_of(const double *freqs, int32_t nchan);
 int64_t delay_of(double dm, double f, double fref, double tsamp, int32_t D);
@@ -113,6 +126,9 @@ std::string plan_key(const gsp_dmt_desc *desc, const double *freqs);
 
 // Dedispersion (dedisp.hip)
 DedispShape default_shape(int32_t D);
+bool shape_supported(const DedispShape &s);
+std::string row_signature(const gsp_dmt_desc *desc, int32_t s);
+DedispShape shape_for_row(gsp_ctx *ctx, const gsp_dmt_desc *desc, int32_t s);
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
                       const DedispShape &shape, RowTables &rt);
 void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st);
@@ -139,4 +155,25 @@ void launch_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, c
                    int32_t n_widths, int32_t max_width, float thr, Frag *frags, int64_t cap,
                    unsigned long long *counter, hipStream_t st);
 
+}  // namespace gsp
+
+namespace gsp {
+template <class F>
+int guarded(gsp_ctx *ctx, F &&f) {
+  try {
+    if (ctx) check_hip(hipSetDevice(ctx->device), "select device");
+    f();
+    if (ctx) ctx->last_error.clear();
+    return GSP_OK;
+  } catch (const Error &e) {
+    if (ctx) ctx->last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return GSP_ENOMEM;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unexpected internal error";
+    return GSP_EDEVICE;
+  }
+}
 }  // namespace gsp

@@ -64,6 +64,22 @@ _L.gsp_trial_stats.argtypes = [P, P, C.POINTER(DmtDesc), P, P, P]
 _L.gsp_single_pulse_search.restype = C.c_int
 _L.gsp_single_pulse_search.argtypes = [P, P, C.POINTER(DmtDesc), P, C.c_int32, C.c_float, P, C.c_int64,
                                        C.POINTER(C.c_int64), P]
+class Shape(C.Structure):
+    _fields_ = [("groups", C.c_int32), ("tpw", C.c_int32), ("waves", C.c_int32), ("chunk", C.c_int32)]
+
+
+_L.gsp_autotune.restype = C.c_int
+_L.gsp_autotune.argtypes = [P, P, P, C.POINTER(DmtDesc), P, C.c_int32, P]
+_L.gsp_row_shape.restype = C.c_int
+_L.gsp_row_shape.argtypes = [P, P, C.POINTER(DmtDesc), C.c_int32, C.POINTER(Shape)]
+_L.gsp_set_row_shape.restype = C.c_int
+_L.gsp_set_row_shape.argtypes = [P, P, C.POINTER(DmtDesc), C.c_int32, C.POINTER(Shape)]
+_L.gsp_tuning_save.restype = C.c_int
+_L.gsp_tuning_save.argtypes = [P, C.c_char_p]
+_L.gsp_tuning_load.restype = C.c_int
+_L.gsp_tuning_load.argtypes = [P, C.c_char_p]
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double), ("work", C.c_double)]
 
@@ -163,6 +179,33 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, fb, freqs, desc: DmtDesc, out=None, n_reps: int = 2, stream=None):
+        """Time every candidate launch shape per plan row; keep the fastest."""
+        import torch
+        if out is None:
+            out = torch.empty(desc.total, dtype=torch.int32, device=fb.device)
+        f = _f64(freqs)
+        _check(_L.gsp_autotune(self.h, C.c_void_p(fb.data_ptr()), f.ctypes.data, C.byref(desc),
+                               C.c_void_p(out.data_ptr()), int(n_reps), _stream_handle(stream)), self.h)
+        return [self.row_shape(freqs, desc, s) for s in range(desc.n_seg)]
+
+    def row_shape(self, freqs, desc: DmtDesc, seg: int) -> tuple:
+        f = _f64(freqs)
+        sh = Shape()
+        _check(_L.gsp_row_shape(self.h, f.ctypes.data, C.byref(desc), int(seg), C.byref(sh)), self.h)
+        return (sh.groups, sh.tpw, sh.waves, sh.chunk)
+
+    def set_row_shape(self, freqs, desc: DmtDesc, seg: int, groups: int, tpw: int, waves: int, chunk: int):
+        f = _f64(freqs)
+        sh = Shape(int(groups), int(tpw), int(waves), int(chunk))
+        _check(_L.gsp_set_row_shape(self.h, f.ctypes.data, C.byref(desc), int(seg), C.byref(sh)), self.h)
+
+    def tuning_save(self, path: str):
+        _check(_L.gsp_tuning_save(self.h, path.encode()), self.h)
+
+    def tuning_load(self, path: str):
+        _check(_L.gsp_tuning_load(self.h, path.encode()), self.h)
 
     def profile_enable(self, on: bool = True):
         _check(_L.gsp_profile_enable(self.h, int(bool(on))), self.h)
