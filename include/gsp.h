@@ -154,6 +154,78 @@ int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt_dev, const gsp_dmt_
  * dm_index, then earlier t_peak).  Returns the number of groups via n_groups. */
 int gsp_group_candidates(const gsp_candidate *cands, int64_t n, int64_t *rep_out, int64_t *n_groups);
 
+/* ---- Streaming: continuous batching of beams arriving in blocks ----
+ *
+ * The overlap between consecutive blocks that the paper's dedispersion loop
+ * takes from the previous block (Algorithm 2: lastdata/data; Algorithm 3:
+ * one merged 2*numpts buffer, Section 2.3) is kept on the device per (beam,
+ * plan row): the downsampled samples of the last (maximum delay + one block).
+ * Each block of B raw samples (B a multiple of 4 x every downsampling factor)
+ * yields, per row with downsampling D and maximum delay M, the outputs
+ *     window k = [max(0, N_k - M), max(0, N_{k+1} - M))
+ * (N_k = downsampled samples received before block k): exactly the outputs of
+ * gsp_dedisperse over the beam so far, bit for bit.  Statistics are taken per
+ * (window, trial) over the window's samples; box ends lie in the window and
+ * boxes may reach back up to (max width - 1) samples into earlier windows;
+ * runs are split at window edges.  A beam's results do not depend on which
+ * other beams share its steps.
+ *
+ * One step processes one pending block of every admitted beam with a fixed
+ * sequence of kernels captured once as a hipGraph and replayed.  Beams are
+ * admitted against the device-memory budget; a beam that does not fit is
+ * queued (GSP_EAGAIN, the id stays valid and its blocks are held on the host)
+ * and admitted, in order, when finished beams release memory. */
+typedef struct gsp_stream gsp_stream;
+
+typedef struct gsp_stream_candidate {
+  int32_t beam;   /* beam id */
+  int32_t block;  /* index of the beam's block whose window held the run */
+  gsp_candidate c; /* times in absolute samples of the row since the beam's start */
+} gsp_stream_candidate;
+
+typedef struct gsp_stream_stats {
+  double lat_p50_s, lat_p99_s, lat_max_s; /* push -> results on the host, per block */
+  int64_t blocks, steps;
+  double busy_s;                          /* wall time inside steps */
+  int64_t mem_used, mem_budget;           /* device bytes held by admitted beams */
+  int32_t beams_active, beams_queued;
+  int64_t blocks_pending;
+} gsp_stream_stats;
+
+/* widths/threshold: the search of every beam (as gsp_single_pulse_search). */
+int gsp_stream_create(gsp_ctx *ctx, int64_t mem_budget_bytes, int32_t block_nsamp, const int32_t *widths,
+                      int32_t n_widths, float threshold, gsp_stream **out);
+void gsp_stream_destroy(gsp_stream *s);
+const char *gsp_stream_last_error(const gsp_stream *s);
+/* GSP_OK: admitted; GSP_EAGAIN: queued (beam_id valid); GSP_ENOMEM: larger than the budget. */
+int gsp_stream_open_beam(gsp_stream *s, int32_t nchan, const double *freqs_mhz, double tsamp_s,
+                         const gsp_segment *segs, int32_t n_seg, int32_t *beam_id);
+/* block_host: uint8 [nsamp][nchan] time-major, copied before return;
+ * nsamp < block_nsamp marks the beam's last block. */
+int gsp_stream_push(gsp_stream *s, int32_t beam_id, const uint8_t *block_host, int64_t nsamp);
+/* No more blocks; the beam's memory is released after its last block. */
+int gsp_stream_close_beam(gsp_stream *s, int32_t beam_id);
+/* Caller-driven processing: one step (*n_blocks = blocks processed, 0 if idle). */
+int gsp_stream_step(gsp_stream *s, int64_t *n_blocks);
+/* Library-driven processing: a worker thread steps whenever blocks are pending. */
+int gsp_stream_start(gsp_stream *s);
+int gsp_stream_stop(gsp_stream *s);
+/* Wait until every pushed block of the admitted beams is processed. */
+int gsp_stream_flush(gsp_stream *s);
+/* Drain up to cap candidates found so far (in step order). */
+int gsp_stream_poll(gsp_stream *s, gsp_stream_candidate *out, int64_t cap, int64_t *n);
+int gsp_stream_report(gsp_stream *s, gsp_stream_stats *out);
+/* The last step's window of row `seg`: host int32 [n_dm][*n_t], outputs
+ * *t_first .. *t_first + *n_t - 1 (worker stopped). */
+int gsp_stream_window(gsp_stream *s, int32_t beam_id, int32_t seg, int32_t *host_out, int64_t cap, int64_t *t_first,
+                      int64_t *n_t);
+/* Beam state (rings, look-back, counters) to/from host memory; restore into a
+ * freshly opened beam with the same plan continues bit-identically. */
+int gsp_stream_snapshot(gsp_stream *s, int32_t beam_id, void *host_buf, int64_t cap, int64_t *bytes);
+int gsp_stream_restore(gsp_stream *s, int32_t beam_id, const void *host_buf, int64_t bytes);
+/* 1 (default): replay the captured step graph; 0: launch the kernels directly. */
+int gsp_stream_set_graph(gsp_stream *s, int enable);
+
 /* Launch shape of the dedispersion kernel for one plan row: each workgroup
  * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials
  * over 128*`groups` output samples; `chunk` channels are staged into LDS per

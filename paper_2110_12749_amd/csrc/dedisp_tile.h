@@ -1,0 +1,261 @@
+// Device code of the dedispersion tile, shared by the batch launch
+// (dedisp.hip) and the streaming launch (stream.hip).
+#pragma once
+
+#include "gsp_internal.h"
+
+namespace gsp {
+
+struct DedispArgs {
+  const void *Y;            // channel-major staged input (uint8 or uint16)
+  int64_t pitch;            // elements per channel row of Y
+  const uint32_t *addr;     // [nchan][n_dm_pad] LDS dword offsets
+  const int32_t *base;      // [n_tiles_dm][nchan] staging start (delay of tile's first trial, /4*4)
+  int32_t *out;             // out[i * out_pitch + (t - t_lo)] for t in [t_lo, t_hi)
+  int64_t out_pitch;
+  int64_t t_origin;         // absolute output index of tile 0's first sample (multiple of 4)
+  int64_t t_lo, t_hi;       // outputs stored
+  int64_t ring;             // staged samples per channel in a ring (0: linear copy)
+  int64_t phys0;            // position of sample t_origin in the staged row (multiple of 4)
+  int32_t n_dm, n_dm_pad, nchan;
+  int32_t chunk;            // channels per staging pass
+  int32_t flush;            // channels between flushes of the 16-bit lanes
+  int32_t row_dw;           // dwords per staged copy of a channel
+  int32_t n_dm_tiles, n_t_tiles;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  // hardware dispatches workgroup b to XCD b % 8; give each XCD a contiguous
+  // range of logical tiles
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, k = b >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Staging unit: 16 consecutive samples of one channel, i.e. 8 dwords of each
+// LDS copy.  Each thread stages at most kUnitMax units per chunk.
+static constexpr int kUnitMax = 2;
+
+template <typename SrcT>
+struct Unit {
+  static constexpr int W = 16 / (4 / sizeof(SrcT));  // source dwords holding 16 samples
+  uint32_t w[W];
+  uint32_t tail;  // sample 16 (needed by the shifted copy)
+};
+
+// One tile: trials [dm_tile*MT, +MT) x outputs t0 + [0, 128*K) with
+// t0 = t_origin + t_tile * 128*K.  Every thread of the workgroup calls it.
+template <int K, int TPW, typename SrcT>
+__device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, int t_tile, uint32_t *lds) {
+  static_assert(TPW % 4 == 0, "offsets are read four trials at a time");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nthreads = blockDim.x;
+  const int nwaves = nthreads >> 6;
+  constexpr int T = 128 * K;
+  const int64_t t_rel = (int64_t)t_tile * T;  // tile start relative to t_origin
+  const int64_t t0 = a.t_origin + t_rel;
+  const int MT = TPW * nwaves;
+  const int i_tile = dm_tile * MT;
+  const int row_dw = a.row_dw;  // multiple of 8
+  const int U = row_dw >> 3;    // staging units per channel
+  const int chunk = a.chunk;
+  const int n_chunks = (a.nchan + chunk - 1) / chunk;
+  // LDS: samples [chunk][2][row_dw] | offsets [chunk][MT] | staging bases [2][chunk]
+  uint32_t *data = lds;
+  uint32_t *offs = lds + 2 * chunk * row_dw;
+  int32_t *bases = reinterpret_cast<int32_t *>(offs + chunk * MT);
+
+  const SrcT *Y = static_cast<const SrcT *>(a.Y);
+  const int32_t *base_row = a.base + (int64_t)dm_tile * a.nchan;
+
+  // ---- staging helpers ----
+  Unit<SrcT> pu[kUnitMax];
+  uint32_t poff = 0;
+  auto prefetch = [&](int j) {  // global -> registers for chunk j (bases of j already in LDS)
+    const int cs = j * chunk, ce = min(cs + chunk, a.nchan);
+    const int nu = (ce - cs) * U;
+    const int32_t *bj = bases + (j & 1) * chunk;
+    // all addresses first, then all loads, so every load is issued back to back
+    const SrcT *rows[kUnitMax];
+#pragma unroll
+    for (int i = 0; i < kUnitMax; ++i) {
+      const int u = min(tid + i * nthreads, nu - 1);  // clamped: loads stay in bounds
+      const int cl = u / U;
+      const int p = u - cl * U;
+      const int64_t e0 = t0 + bj[cl] + 16 * (int64_t)p;  // multiple of 4
+      rows[i] = Y + (int64_t)(cs + cl) * a.pitch + e0;
+    }
+#pragma unroll
+    for (int i = 0; i < kUnitMax; ++i) {
+      const uint32_t *w = reinterpret_cast<const uint32_t *>(rows[i]);
+#pragma unroll
+      for (int m = 0; m < Unit<SrcT>::W; ++m) pu[i].w[m] = w[m];
+      pu[i].tail = rows[i][16];
+    }
+    if (tid < (ce - cs) * MT) poff = a.addr[(int64_t)(cs + tid / MT) * a.n_dm_pad + i_tile + tid % MT];
+  };
+  auto store = [&](int j) {  // registers -> LDS for chunk j
+    const int cs = j * chunk, ce = min(cs + chunk, a.nchan);
+    const int nu = (ce - cs) * U;
+#pragma unroll
+    for (int i = 0; i < kUnitMax; ++i) {
+      const int u = tid + i * nthreads;
+      if (u < nu) {
+        const int cl = u / U;
+        const int p = u - cl * U;
+        uint32_t c0[8], c1[8];
+        if constexpr (sizeof(SrcT) == 1) {
+          // samples y0..y15 in 4 dwords, y16 in tail
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const uint32_t w = pu[i].w[m >> 1];
+            const uint32_t wn = (m >> 1) + 1 < 4 ? pu[i].w[(m >> 1) + 1] : pu[i].tail;
+            const int b = (m & 1) * 2;  // byte of sample 2m within w
+            const uint32_t ya = (w >> (8 * b)) & 0xFFu;
+            const uint32_t yb = (w >> (8 * b + 8)) & 0xFFu;
+            const uint32_t yc = b == 2 ? (wn & 0xFFu) : ((w >> (8 * b + 16)) & 0xFFu);
+            c0[m] = ya | (yb << 16);
+            c1[m] = yb | (yc << 16);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const uint32_t w = pu[i].w[m];
+            const uint32_t nxt = m + 1 < 8 ? (pu[i].w[m + 1] & 0xFFFFu) : (pu[i].tail & 0xFFFFu);
+            c0[m] = w;
+            c1[m] = (w >> 16) | (nxt << 16);
+          }
+        }
+        uint4 *d0 = reinterpret_cast<uint4 *>(data + (cl * 2) * row_dw + 8 * p);
+        uint4 *d1 = reinterpret_cast<uint4 *>(data + (cl * 2 + 1) * row_dw + 8 * p);
+        d0[0] = make_uint4(c0[0], c0[1], c0[2], c0[3]);
+        d0[1] = make_uint4(c0[4], c0[5], c0[6], c0[7]);
+        d1[0] = make_uint4(c1[0], c1[1], c1[2], c1[3]);
+        d1[1] = make_uint4(c1[4], c1[5], c1[6], c1[7]);
+      }
+    }
+    if (tid < (ce - cs) * MT) offs[tid] = poff;
+  };
+
+  // ---- accumulators ----
+  uint32_t acc[TPW][K];
+  int32_t tot[TPW][K][2];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[j][k] = 0;
+      tot[j][k][0] = 0;
+      tot[j][k][1] = 0;
+    }
+  int since_flush = 0;
+  auto add_flush = [&](uint32_t (*x)[K]) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[j][k] += x[j][k];
+    if (++since_flush == a.flush) {
+      since_flush = 0;
+#pragma unroll
+      for (int j = 0; j < TPW; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          tot[j][k][0] += (int32_t)(acc[j][k] & 0xFFFFu);
+          tot[j][k][1] += (int32_t)(acc[j][k] >> 16);
+          acc[j][k] = 0;
+        }
+    }
+  };
+  auto load_off = [&](const uint32_t *p, uint32_t *o) {
+#pragma unroll
+    for (int j = 0; j < TPW; j += 4) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(p + j);
+      o[j] = q.x;
+      o[j + 1] = q.y;
+      o[j + 2] = q.z;
+      o[j + 3] = q.w;
+    }
+  };
+  auto load_v = [&](const uint32_t *o, uint32_t (*dst)[K]) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const uint32_t *src = data + o[j] + lane;
+#pragma unroll
+      for (int k = 0; k < K; ++k) dst[j][k] = src[64 * k];
+    }
+  };
+
+  // ---- prologue: bases of chunks 0 (LDS) and 1 (register), samples of chunk 0 ----
+  if (tid < chunk) bases[tid] = tid < a.nchan ? base_row[tid] : 0;
+  int32_t pbase = (tid < chunk && chunk + tid < a.nchan) ? base_row[chunk + tid] : 0;
+  __syncthreads();
+  prefetch(0);
+
+  for (int kc = 0; kc < n_chunks; ++kc) {
+    const int cs = kc * chunk, ce = min(cs + chunk, a.nchan);
+    __syncthreads();  // every wave is done with chunk kc-1
+    store(kc);
+    if (tid < chunk) bases[((kc + 1) & 1) * chunk + tid] = pbase;
+    __syncthreads();
+    // in flight during the accumulation below: samples of chunk kc+1, bases of kc+2
+    if (kc + 2 < n_chunks && tid < chunk)
+      pbase = (kc + 2) * chunk + tid < a.nchan ? base_row[(kc + 2) * chunk + tid] : 0;
+    if (kc + 1 < n_chunks) prefetch(kc + 1);
+
+    // ---- accumulate chunk kc: per channel TPW trials x K dwords per lane ----
+    // two register sets: while one channel is added, the next one's samples
+    // and the one after's offsets are in flight (LDS returns in order).  The
+    // loads are unconditional (channel index clamped to the chunk) so that no
+    // branch forces a full wait before the adds.
+    const uint32_t *orow = offs + wave * TPW;
+    const int last = ce - 1 - cs;
+    uint32_t offA[TPW], offB[TPW], vA[TPW][K], vB[TPW][K];
+    load_off(orow, offA);
+    load_v(offA, vA);
+    load_off(orow + min(1, last) * MT, offB);
+    for (int c = 0; c <= last; c += 2) {
+      load_v(offB, vB);
+      load_off(orow + min(c + 2, last) * MT, offA);
+      add_flush(vA);
+      if (c + 1 > last) break;
+      load_v(offA, vA);
+      load_off(orow + min(c + 3, last) * MT, offB);
+      add_flush(vB);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TPW; ++j)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      tot[j][k][0] += (int32_t)(acc[j][k] & 0xFFFFu);
+      tot[j][k][1] += (int32_t)(acc[j][k] >> 16);
+    }
+  // ---- store ----
+  const int i_wave = i_tile + wave * TPW;
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int i = i_wave + j;
+    if (i >= a.n_dm) break;
+    int32_t *orow_out = a.out + (int64_t)i * a.out_pitch - a.t_lo;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
+      if (t >= a.t_lo && t < a.t_hi) orow_out[t] = tot[j][k][0];
+      if (t + 1 >= a.t_lo && t + 1 < a.t_hi) orow_out[t + 1] = tot[j][k][1];
+    }
+  }
+}
+
+// Batch launch: one tile per workgroup, XCD-aware tile order.
+template <int K, int TPW, typename SrcT>
+__global__ __launch_bounds__(512) void k_dedisp(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int G = a.n_dm_tiles * a.n_t_tiles;
+  const int L = xcd_remap(blockIdx.x, G);
+  dedisp_tile<K, TPW, SrcT>(a, L % a.n_dm_tiles, L / a.n_dm_tiles, lds);
+}
+
+
+}  // namespace gsp

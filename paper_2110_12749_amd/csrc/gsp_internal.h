@@ -72,6 +72,46 @@ struct PlanCache {
   std::vector<std::unique_ptr<RowTables>> rows;
 };
 
+struct Frag {  // one run of flagged box ends inside a search tile
+  int32_t trial;    // global trial index
+  int32_t width;    // peak width
+  int64_t t_first;  // first box end
+  int64_t t_last;   // last box end
+  int64_t e_peak;   // box end of the peak
+  double snr;
+  int32_t open_left;   // run starts at the tile's first box end (tile > 0)
+  int32_t open_right;  // run ends at the tile's last box end (not the series end)
+};
+static_assert(sizeof(Frag) == 48, "fragment layout");
+
+// A series job: the n_dm trials of one plan row, each a row of `pitch` int32
+// samples.  Box ends and statistics cover [e_begin, e_begin + n); boxes may
+// start up to `look` samples before e_begin.  Reported times are
+// abs0 + (index - e_begin).
+struct SeriesJob {
+  const int32_t *x;
+  int64_t pitch;
+  int64_t e_begin;
+  int64_t n;
+  int64_t look;
+  int64_t abs0;
+  int64_t tiles;   // search tiles per trial (finalize_table)
+  int64_t block0;  // first search item of the job (finalize_table)
+  int32_t n_dm;
+  int32_t trial0;  // global trial index of the job's first trial (finalize_table)
+};
+static constexpr int kMaxJobs = 1024;
+struct SeriesTable {
+  SeriesJob job[kMaxJobs];
+  int32_t n_jobs = 0;
+  int32_t n_trials = 0;
+  int64_t n_items = 0;
+};
+struct SearchTiling {
+  int per = 16;     // prefix entries per thread
+  int tile = 0;     // box ends per search item
+  size_t lds = 0;   // dynamic LDS of the search kernel
+};
 }  // namespace gsp
 
 struct gsp_ctx;
@@ -92,6 +132,8 @@ struct gsp_ctx {
   gsp::DevBuf frags;       // search run fragments
   gsp::DevBuf counter;     // fragment counter
   gsp::DevBuf widths;      // device copy of the width set
+  gsp::DevBuf jobs;        // device copy of the series-job table
+  std::unique_ptr<gsp::SeriesTable> jobs_host = std::make_unique<gsp::SeriesTable>();
   std::vector<uint8_t> host_scratch;
   // tuned shapes keyed by row signature
   std::map<std::string, gsp::DedispShape> tuned;
@@ -136,17 +178,15 @@ void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStrea
 int64_t staged_pitch(const RowTables &rt);
 
 // Search (search.hip)
-struct Frag {  // one run of flagged box ends inside a search tile
-  int32_t trial;    // global trial index
-  int32_t width;    // peak width
-  int64_t t_first;  // first box end
-  int64_t t_last;   // last box end
-  int64_t e_peak;   // box end of the peak
-  double snr;
-  int32_t open_left;   // run starts at the tile's first box end (tile > 0)
-  int32_t open_right;  // run ends at the tile's last box end (not the series end)
-};
-static_assert(sizeof(Frag) == 48, "fragment layout");
+SearchTiling search_tiling(int32_t max_width);
+void set_search_attributes(const SearchTiling &tl);
+void finalize_table(SeriesTable &t, const SearchTiling &tl);
+void launch_stats_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, double *musig, double bytes,
+                        hipStream_t st);
+void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, const SearchTiling &tl,
+                         const double *musig, const int32_t *widths_dev, int32_t n_widths, int32_t max_width,
+                         float thr, Frag *frags, int64_t cap, unsigned long long *counter, double bytes,
+                         hipStream_t st);
 
 void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
 // Device pointer of per-trial mu/sigma (double[2*n_trials]) after launch_stats.

@@ -280,3 +280,156 @@ def single_pulse_search(dmt, desc: DmtDesc, widths, threshold: float, ctx: Conte
 def trial_stats(dmt, desc: DmtDesc, ctx: Context | None = None, stream=None):
     ctx = ctx or context(dmt.device.index or 0)
     return ctx.trial_stats(dmt, desc, stream=stream)
+
+
+# ---------------------------------------------------------------------------
+# streaming (continuous batching of beams arriving in blocks)
+# ---------------------------------------------------------------------------
+class StreamCandidate(C.Structure):
+    _fields_ = [("beam", C.c_int32), ("block", C.c_int32), ("c", Candidate)]
+
+
+class StreamStats(C.Structure):
+    _fields_ = [("lat_p50_s", C.c_double), ("lat_p99_s", C.c_double), ("lat_max_s", C.c_double),
+                ("blocks", C.c_int64), ("steps", C.c_int64), ("busy_s", C.c_double), ("mem_used", C.c_int64),
+                ("mem_budget", C.c_int64), ("beams_active", C.c_int32), ("beams_queued", C.c_int32),
+                ("blocks_pending", C.c_int64)]
+
+
+STREAM_CAND_DTYPE = np.dtype([("beam", np.int32), ("block", np.int32)] + [(n, CAND_DTYPE[n]) for n in CAND_DTYPE.names])
+assert STREAM_CAND_DTYPE.itemsize == C.sizeof(StreamCandidate)
+
+_L.gsp_stream_create.restype = C.c_int
+_L.gsp_stream_create.argtypes = [P, C.c_int64, C.c_int32, P, C.c_int32, C.c_float, C.POINTER(P)]
+_L.gsp_stream_destroy.restype = None
+_L.gsp_stream_destroy.argtypes = [P]
+_L.gsp_stream_last_error.restype = C.c_char_p
+_L.gsp_stream_last_error.argtypes = [P]
+_L.gsp_stream_open_beam.restype = C.c_int
+_L.gsp_stream_open_beam.argtypes = [P, C.c_int32, P, C.c_double, P, C.c_int32, C.POINTER(C.c_int32)]
+_L.gsp_stream_push.restype = C.c_int
+_L.gsp_stream_push.argtypes = [P, C.c_int32, P, C.c_int64]
+_L.gsp_stream_close_beam.restype = C.c_int
+_L.gsp_stream_close_beam.argtypes = [P, C.c_int32]
+_L.gsp_stream_step.restype = C.c_int
+_L.gsp_stream_step.argtypes = [P, C.POINTER(C.c_int64)]
+for _n in ("gsp_stream_start", "gsp_stream_stop", "gsp_stream_flush"):
+    getattr(_L, _n).restype = C.c_int
+    getattr(_L, _n).argtypes = [P]
+_L.gsp_stream_poll.restype = C.c_int
+_L.gsp_stream_poll.argtypes = [P, P, C.c_int64, C.POINTER(C.c_int64)]
+_L.gsp_stream_report.restype = C.c_int
+_L.gsp_stream_report.argtypes = [P, C.POINTER(StreamStats)]
+_L.gsp_stream_window.restype = C.c_int
+_L.gsp_stream_window.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+_L.gsp_stream_snapshot.restype = C.c_int
+_L.gsp_stream_snapshot.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
+_L.gsp_stream_restore.restype = C.c_int
+_L.gsp_stream_restore.argtypes = [P, C.c_int32, P, C.c_int64]
+_L.gsp_stream_set_graph.restype = C.c_int
+_L.gsp_stream_set_graph.argtypes = [P, C.c_int]
+
+
+class Stream:
+    """A streaming engine (gsp_stream_create) on a context."""
+
+    def __init__(self, ctx: Context, mem_budget: int, block_nsamp: int, widths, threshold: float):
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        h = P()
+        _check(_L.gsp_stream_create(ctx.h, int(mem_budget), int(block_nsamp), w.ctypes.data, len(w),
+                                    float(threshold), C.byref(h)), ctx.h)
+        self.h = h
+        self.ctx = ctx
+        self.block = int(block_nsamp)
+        self.nchan = {}
+
+    def _check(self, st):
+        if st != GSP_OK:
+            raise GspError(st, _L.gsp_stream_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            _L.gsp_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open_beam(self, nchan: int, freqs, tsamp: float, segments):
+        """Returns (beam_id, admitted)."""
+        f = _f64(freqs)
+        segs = _segs(segments)
+        bid = C.c_int32()
+        st = _L.gsp_stream_open_beam(self.h, int(nchan), f.ctypes.data, float(tsamp), C.addressof(segs),
+                                     len(segments), C.byref(bid))
+        if st not in (GSP_OK, GSP_EAGAIN):
+            self._check(st)
+        self.nchan[bid.value] = int(nchan)
+        return bid.value, st == GSP_OK
+
+    def push(self, beam: int, block: np.ndarray):
+        b = np.ascontiguousarray(block, dtype=np.uint8)
+        assert b.ndim == 2 and b.shape[1] == self.nchan[beam]
+        self._check(_L.gsp_stream_push(self.h, int(beam), b.ctypes.data, b.shape[0]))
+
+    def close_beam(self, beam: int):
+        self._check(_L.gsp_stream_close_beam(self.h, int(beam)))
+
+    def step(self) -> int:
+        n = C.c_int64()
+        self._check(_L.gsp_stream_step(self.h, C.byref(n)))
+        return n.value
+
+    def start(self):
+        self._check(_L.gsp_stream_start(self.h))
+
+    def stop(self):
+        self._check(_L.gsp_stream_stop(self.h))
+
+    def flush(self):
+        self._check(_L.gsp_stream_flush(self.h))
+
+    def set_graph(self, on: bool):
+        self._check(_L.gsp_stream_set_graph(self.h, int(bool(on))))
+
+    def poll(self) -> np.ndarray:
+        rows = []
+        while True:
+            buf = np.zeros(4096, STREAM_CAND_DTYPE)
+            n = C.c_int64()
+            self._check(_L.gsp_stream_poll(self.h, buf.ctypes.data, len(buf), C.byref(n)))
+            rows.append(buf[: n.value])
+            if n.value < len(buf):
+                break
+        return np.concatenate(rows)
+
+    def report(self) -> dict:
+        r = StreamStats()
+        self._check(_L.gsp_stream_report(self.h, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in StreamStats._fields_}
+
+    def window(self, beam: int, seg: int, n_dm: int):
+        """(t_first, int32 [n_dm][n_t]) of the last step's window of a row."""
+        t0 = C.c_int64()
+        nt = C.c_int64()
+        self._check(_L.gsp_stream_window(self.h, int(beam), int(seg), None, 0, C.byref(t0), C.byref(nt)))
+        out = np.empty((n_dm, nt.value), np.int32)
+        if nt.value > 0:
+            self._check(_L.gsp_stream_window(self.h, int(beam), int(seg), out.ctypes.data, out.size, C.byref(t0),
+                                             C.byref(nt)))
+        return t0.value, out
+
+    def snapshot(self, beam: int) -> bytes:
+        n = C.c_int64()
+        st = _L.gsp_stream_snapshot(self.h, int(beam), None, 0, C.byref(n))
+        if st not in (GSP_OK, GSP_ECAPACITY):
+            self._check(st)
+        buf = C.create_string_buffer(n.value)
+        self._check(_L.gsp_stream_snapshot(self.h, int(beam), buf, n.value, C.byref(n)))
+        return buf.raw
+
+    def restore(self, beam: int, data: bytes):
+        self._check(_L.gsp_stream_restore(self.h, int(beam), data, len(data)))

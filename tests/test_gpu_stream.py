@@ -1,0 +1,226 @@
+"""Streaming engine: block-by-block results equal the oracle's window
+semantics, a beam's results are the same alone and in a mix of beams,
+admission by memory queues and later admits beams, snapshot/restore
+continues bit-identically, graph replay equals direct launches."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_12749_amd import synth
+from tests._util import match_candidates, oracle_cands_with_seg, say
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [1, 2, 4, 8, 16, 32]
+THR = 6.0
+BLOCK = 512
+
+
+def beam_workload(k, nchan=64, nsamp=3000, segs=None):
+    if segs is None:
+        segs = [(0.0, 1.0, 40, 1), (40.0, 2.0, 13, 2)]
+    w = synth.small(nchan=nchan, nsamp=nsamp, segments=segs, n_pulses=2, seed_offset=10 + k, widths=WIDTHS)
+    return w
+
+
+def windows_of(w, desc):
+    """Per block k and row r: (a, b) output window."""
+    nblk = (w.nsamp + BLOCK - 1) // BLOCK
+    out = []
+    for k in range(nblk):
+        rows = []
+        for r, seg in enumerate(w.segments):
+            D = seg[3]
+            M = desc.max_delay[r]
+            N0 = (k * BLOCK) // D
+            N1 = N0 + min(BLOCK, w.nsamp - k * BLOCK) // D
+            rows.append((max(0, N0 - M), max(0, N1 - M)))
+        out.append(rows)
+    return out
+
+
+def oracle_window_cands(full, w, r, a, b):
+    rows = []
+    for i in range(full.shape[0]):
+        c = oracle.search_window(full[i], a, b, WIDTHS, THR, trial=i)
+        if len(c):
+            rows.append(c)
+    c = np.concatenate(rows) if rows else np.zeros(0, oracle.CAND_DTYPE)
+    return oracle_cands_with_seg([(r, c)])
+
+
+@pytest.fixture(scope="module")
+def env(dev):
+    import torch
+    from paper_2110_12749_amd import gsp
+    ctx = gsp.Context(0)
+    yield gsp, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def run_beams(env, beams, interleave=True, graph=True, budget=1 << 34, check_windows=None):
+    """Push every beam's blocks (round robin) and step; returns per-beam candidates."""
+    gsp, ctx, torch = env
+    s = gsp.Stream(ctx, budget, BLOCK, WIDTHS, THR)
+    s.set_graph(graph)
+    ids = []
+    for w, X in beams:
+        bid, ok = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
+        ids.append(bid)
+    nblk = max((w.nsamp + BLOCK - 1) // BLOCK for w, _ in beams)
+    for k in range(nblk):
+        for (w, X), bid in zip(beams, ids):
+            if k * BLOCK < w.nsamp:
+                s.push(bid, X[k * BLOCK: (k + 1) * BLOCK])
+        while s.step():
+            if check_windows:
+                check_windows(s, ids, k)
+            break
+    s.flush()
+    cands = s.poll()
+    rep = s.report()
+    s.close()
+    return ids, cands, rep
+
+
+def test_single_beam_windows_and_candidates_match_oracle(env):
+    gsp, ctx, torch = env
+    w = beam_workload(0, nsamp=3000)
+    X = w.generate()
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    full = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    wins = windows_of(w, desc)
+    say(f"[case] single beam, max delays {list(desc.max_delay)[:2]}, windows {wins}")
+    seen = []
+
+    def check(s, ids, k):
+        for r, seg in enumerate(w.segments):
+            t0, arr = s.window(ids[0], r, seg[2])
+            a, b = wins[k][r]
+            assert (t0, arr.shape[1]) == (a, b - a), (k, r)
+            assert (arr == full[r][:, a:b]).all(), (k, r)
+            seen.append((k, r, b - a))
+
+    ids, cands, rep = run_beams(env, [(w, X)], check_windows=check)
+    assert any(n == 0 for _, _, n in seen) and any(n > 0 for _, _, n in seen)
+    # candidates window by window
+    for k, rows in enumerate(wins):
+        for r, (a, b) in enumerate(rows):
+            co = oracle_window_cands(full[r], w, r, a, b)
+            cg = cands[(cands["block"] == k) & (cands["seg"] == r)]
+            match_candidates(cg, co, THR)
+    assert rep["blocks"] == len(wins)
+
+
+def test_mix_equals_alone_and_oracle(env):
+    gsp, ctx, torch = env
+    cfgs = [dict(nchan=64, nsamp=2900), dict(nchan=96, nsamp=1800, segs=[(0.0, 0.5, 37, 1)]),
+            dict(nchan=48, nsamp=3700, segs=[(10.0, 1.5, 21, 2), (41.5, 3.0, 9, 4)]), dict(nchan=64, nsamp=700)]
+    beams = []
+    for k, c in enumerate(cfgs):
+        w = beam_workload(k + 1, **c)
+        beams.append((w, w.generate()))
+    _, mix, rep = run_beams(env, beams)
+    say(f"  mix: {len(mix)} candidates, report {rep}")
+    for j, (w, X) in enumerate(beams):
+        _, alone, _ = run_beams(env, [(w, X)])
+        m = mix[mix["beam"] == j]
+        key = ["block", "seg", "dm_index", "t_first", "t_last", "t_peak", "width"]
+        a_sorted = np.sort(alone[key])
+        m_sorted = np.sort(m[key])
+        assert len(a_sorted) == len(m_sorted) and (a_sorted == m_sorted).all(), j
+        assert np.allclose(np.sort(alone["snr"]), np.sort(m["snr"]), rtol=0, atol=0)
+        # and against the oracle, window by window
+        desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+        full = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+        for k, rows in enumerate(windows_of(w, desc)):
+            for r, (a, b) in enumerate(rows):
+                co = oracle_window_cands(full[r], w, r, a, b)
+                match_candidates(m[(m["block"] == k) & (m["seg"] == r)], co, THR)
+
+
+def test_graph_replay_equals_direct_launch(env):
+    w = beam_workload(7, nsamp=2600)
+    X = w.generate()
+    _, c1, _ = run_beams(env, [(w, X)], graph=True)
+    _, c2, _ = run_beams(env, [(w, X)], graph=False)
+    assert len(c1) == len(c2) and (np.sort(c1, order=["block", "seg", "dm_index", "t_first"]) ==
+                                   np.sort(c2, order=["block", "seg", "dm_index", "t_first"])).all()
+
+
+def test_admission_queues_and_admits_later(env):
+    gsp, ctx, torch = env
+    w0 = beam_workload(11, nsamp=1100)
+    w1 = beam_workload(12, nsamp=1600)
+    w2 = beam_workload(13, nsamp=1500)
+    s0 = gsp.Stream(ctx, 1 << 34, BLOCK, WIDTHS, THR)
+    # measure one beam's footprint, then budget for two
+    bid, _ = s0.open_beam(w0.nchan, w0.freqs, w0.tsamp, w0.segments)
+    one = s0.report()["mem_used"]
+    s0.close()
+    s = gsp.Stream(ctx, 2 * one + one // 2, BLOCK, WIDTHS, THR)
+    ids = [s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments) for w in (w0, w1, w2)]
+    assert [ok for _, ok in ids] == [True, True, False]
+    X = [w.generate() for w in (w0, w1, w2)]
+    for k in range(4):
+        for j, w in enumerate((w0, w1, w2)):
+            if k * BLOCK < w.nsamp:
+                s.push(ids[j][0], X[j][k * BLOCK:(k + 1) * BLOCK])
+        s.step()
+    assert s.report()["beams_queued"] == 0  # beam 0 ended -> beam 2 admitted
+    s.flush()
+    mix = s.poll()
+    s.close()
+    _, alone, _ = run_beams(env, [(w2, X[2])])
+    m = mix[mix["beam"] == ids[2][0]]
+    assert len(m) == len(alone)
+    assert (np.sort(m[["block", "seg", "dm_index", "t_peak", "width"]]) ==
+            np.sort(alone[["block", "seg", "dm_index", "t_peak", "width"]])).all()
+
+
+def test_snapshot_restore_continues_identically(env):
+    gsp, ctx, torch = env
+    w = beam_workload(21, nsamp=3300)
+    X = w.generate()
+    _, ref, _ = run_beams(env, [(w, X)])
+    s = gsp.Stream(ctx, 1 << 34, BLOCK, WIDTHS, THR)
+    bid, _ = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
+    for k in range(3):
+        s.push(bid, X[k * BLOCK:(k + 1) * BLOCK])
+        s.step()
+    first = s.poll()
+    snap = s.snapshot(bid)
+    s.close()
+    s2 = gsp.Stream(ctx, 1 << 34, BLOCK, WIDTHS, THR)
+    bid2, _ = s2.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
+    s2.restore(bid2, snap)
+    for k in range(3, (w.nsamp + BLOCK - 1) // BLOCK):
+        s2.push(bid2, X[k * BLOCK:(k + 1) * BLOCK])
+        s2.step()
+    rest = s2.poll()
+    s2.close()
+    got = np.concatenate([first, rest])
+    key = ["block", "seg", "dm_index", "t_first", "t_last", "t_peak", "width"]
+    assert len(got) == len(ref) and (np.sort(got[key]) == np.sort(ref[key])).all()
+
+
+def test_worker_thread_and_latency_report(env):
+    gsp, ctx, torch = env
+    w = beam_workload(31, nsamp=2500)
+    X = w.generate()
+    _, ref, _ = run_beams(env, [(w, X)])
+    s = gsp.Stream(ctx, 1 << 34, BLOCK, WIDTHS, THR)
+    bid, _ = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
+    s.start()
+    for k in range((w.nsamp + BLOCK - 1) // BLOCK):
+        s.push(bid, X[k * BLOCK:(k + 1) * BLOCK])
+    s.flush()
+    s.stop()
+    got = s.poll()
+    rep = s.report()
+    s.close()
+    assert rep["blocks"] == (w.nsamp + BLOCK - 1) // BLOCK
+    assert 0 < rep["lat_p50_s"] <= rep["lat_p99_s"] <= rep["lat_max_s"]
+    key = ["block", "seg", "dm_index", "t_first", "t_last", "t_peak", "width"]
+    assert (np.sort(got[key]) == np.sort(ref[key])).all()
