@@ -271,6 +271,82 @@ typedef struct gsp_kernel_stat {
 int gsp_profile_enable(gsp_ctx *ctx, int enable);
 int gsp_profile_read(gsp_ctx *ctx, gsp_kernel_stat *out, int32_t cap, int32_t *n, int reset);
 
+/* ------------------------------------------------------------------------
+ * Learned triage of candidates.  The paper classifies candidates after the
+ * search (Section 2.1 names the step, Section 4 its role before the
+ * database); it does not define a classifier.  Here: two 64 x 64 images per
+ * candidate and a small convolutional network trained on the GPU.
+ * ---------------------------------------------------------------------- */
+
+/* Cutouts of candidates found in a dedispersed plan.  For candidate k (row s,
+ * trial i, peak box start t_peak, width w, all at the row's resolution), with
+ * box end e = t_peak + w - 1 and bin width r = clamp(w / 8, 1, 8):
+ *   image 0, DM-time: trials lo .. lo+63 of row s with
+ *     lo = clamp(i - 32, 0, n_dm - 64) (rows of fewer than 64 trials leave
+ *     the missing lines 0), bins b = 0..63 of r samples each covering
+ *     [e - (64-b) r + 1, e - (63-b) r] (the box ends in the last bin, nothing
+ *     after e is read); bin value = sum of the dedispersed series, samples
+ *     before the start of the data counted at the trial's mean;
+ *   image 1, frequency-time: 64 sub-bands, band j = channels
+ *     [j nchan / 64, (j+1) nchan / 64), each channel shifted by its delay at
+ *     trial i, the same 64 bins at the row's resolution (bin value = sum of
+ *     the band's D-downsampled samples); a bin that starts before the data
+ *     is scaled to r samples from its valid part, one wholly before it takes
+ *     the mean of the band's valid bins;
+ * then each image is z-scored (mean 0, variance 1 over its 4096 pixels; a
+ * constant image becomes 0) and stored as bf16 (round to nearest even).
+ * fb_dev, freqs_mhz, dmt_dev, desc: as for gsp_dedisperse (dmt_dev is its
+ * output for this filterbank).  cands_dev: device gsp_candidate[n] (as
+ * returned by the search, copied to the device).  out_dev: device
+ * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`. */
+int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const int32_t *dmt_dev,
+                const gsp_dmt_desc *desc, const gsp_candidate *cands_dev, int64_t n, uint16_t *out_dev,
+                void *stream);
+
+/* Triage network (input bf16 [n][2][64][64], as gsp_cutouts writes):
+ *   conv3x3(2->16) ReLU maxpool2, conv3x3(16->32) ReLU maxpool2,
+ *   conv3x3(32->64) ReLU maxpool2, conv3x3(64->128) ReLU maxpool2,
+ *   flatten (h, w, c) -> 2048, FC 2048->192 ReLU, FC 192->1 = logit
+ *   (logit > 0: astrophysical).  Convolutions use zero padding 1; max-pool
+ *   ties go to the first position in (row, column) order.
+ * Storage: bf16 activations and weights, fp32 accumulation, fp32 master
+ * weights and biases.  Parameters as one float vector, in this order, per
+ * layer weights then biases:
+ *   conv l: w[cout][3][3][cin] (kernel row, kernel column, input channel),
+ *           b[cout];  fc1: w[192][2048], b[192];  fc2: w[192], b[1].
+ * Loss: mean over the batch of the binary cross-entropy with logits;
+ * optimiser Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected). */
+typedef struct gsp_cnn gsp_cnn;
+int64_t gsp_cnn_num_params(void);
+/* He-uniform weights drawn from `seed` (SplitMix64), zero biases. */
+int gsp_cnn_create(gsp_ctx *ctx, uint64_t seed, gsp_cnn **out);
+void gsp_cnn_destroy(gsp_cnn *cnn);
+/* host float[n], n = gsp_cnn_num_params(); set also clears the Adam state. */
+int gsp_cnn_get_params(gsp_cnn *cnn, float *params_host, int64_t n);
+int gsp_cnn_set_params(gsp_cnn *cnn, const float *params_host, int64_t n);
+int gsp_cnn_save(const gsp_cnn *cnn, const char *path);
+int gsp_cnn_load(gsp_cnn *cnn, const char *path);
+/* logits_dev: device float[n].  x_dev: device bf16 [n][2][64][64].
+ * Synchronises `stream` before it starts (buffers may grow), then runs
+ * asynchronously on it. */
+int gsp_cnn_forward(gsp_cnn *cnn, const uint16_t *x_dev, int64_t n, float *logits_dev, void *stream);
+/* Gradient of the mean loss over the batch with respect to every parameter
+ * (host float[num_params], same order), and the mean loss (host, optional);
+ * labels_dev: device float[n] in {0, 1}.  Parameters are unchanged.
+ * Synchronises `stream`. */
+int gsp_cnn_gradients(gsp_cnn *cnn, const uint16_t *x_dev, const float *labels_dev, int64_t n,
+                      float *grads_host, float *loss_host, void *stream);
+/* One Adam step on the batch with learning rate lr > 0.  loss_host
+ * (optional) receives the batch's mean loss before the step and then the
+ * call synchronises `stream`; without it the step stays asynchronous. */
+int gsp_cnn_train_step(gsp_cnn *cnn, const uint16_t *x_dev, const float *labels_dev, int64_t n, float lr,
+                       float *loss_host, void *stream);
+/* Inspection of the last forward pass (tests): which = 0..3 the pooled
+ * output of convolution block which+1, bf16 [n][h][w][c] (h = w = 32, 16, 8,
+ * 4); 4 the hidden layer, bf16 [n][192]; 5 the logits, float [n].  `bytes`
+ * must equal the size for the batch of the last pass.  Synchronises. */
+int gsp_cnn_activation(gsp_cnn *cnn, int32_t which, void *host_out, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,824 @@
+// Learned triage: candidate cutouts and a small CNN trained on the GPU.
+//
+// Network (channels-last activations, BF16 storage, FP32 accumulation):
+//   input 2 x 64 x 64 (DM-time and frequency-time cutouts)
+//   conv3x3(2->16)+ReLU+maxpool2 -> conv3x3(16->32)+ReLU+maxpool2
+//   -> conv3x3(32->64)+ReLU+maxpool2 -> conv3x3(64->128)+ReLU+maxpool2
+//   -> flatten (h, w, c) 2048 -> FC 192 + ReLU -> FC 1 -> logit
+//   loss: binary cross-entropy with logits (mean over the batch); Adam.
+// Every convolution and fully connected product, forward and backward
+// (activation and weight gradients), runs on one hand-written GEMM kernel
+// built on the gfx950 BF16 matrix cores (v_mfma_f32_32x32x8bf16_1k), fed by
+// im2col / col2im gathers; the epilogue fuses bias, ReLU and gradient masks.
+#include <cmath>
+#include <cstring>
+#include <fstream>
+
+#include "gsp_internal.h"
+
+namespace gsp {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// --- bf16 helpers (round to nearest even) ---
+__host__ __device__ inline uint16_t f2bf(float f) {
+  uint32_t u;
+  u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));  // inf/nan
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  return __builtin_bit_cast(float, u);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[m][n] = sum_k A[m][k] B[k][n] (+ bias[n]) (ReLU) (mask) with
+// arbitrary element strides, BF16 inputs, FP32 accumulation.
+// Workgroup tile 64 x 64, k step 16; 4 waves, each a 32 x 32 MFMA tile.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  const uint16_t *A;
+  int64_t a_m, a_k;  // strides (elements)
+  const uint16_t *B;
+  int64_t b_k, b_n;
+  void *C;
+  int64_t c_m, c_n;
+  int32_t M, N, K;
+  const float *bias;       // [N] or null
+  const uint16_t *mask;    // optional: zero the result where mask[m*c_m + n*c_n] <= 0 (bf16)
+  int32_t relu;
+  int32_t out_bf16;        // 1: store bf16, 0: store fp32
+  int32_t accumulate;      // fp32 output only: C += result
+  int32_t k_chunk;         // split-K: workgroup z covers k in [z*k_chunk, (z+1)*k_chunk); atomic fp32 adds
+};
+
+static constexpr int kTM = 64, kTN = 64, kTK = 16;
+
+static unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 64); }
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ uint16_t As[kTM][kTK + 2];
+  __shared__ uint16_t Bs[kTK][kTN + 2];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * kTM;
+  const int64_t n0 = (int64_t)blockIdx.y * kTN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool split = gridDim.z > 1;
+  const int k_begin = split ? (int)blockIdx.z * g.k_chunk : 0;
+  const int k_end = split ? min(g.K, k_begin + g.k_chunk) : g.K;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
+    // stage A (64 x 16) and B (16 x 64): 4 elements of each per thread
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + u * 256;
+      const int r = e / kTK, c = e % kTK;
+      const int64_t m = m0 + r;
+      const int k = k0 + c;
+      As[r][c] = (m < g.M && k < k_end) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+      const int kr = e / kTN, nc = e % kTN;
+      const int64_t n = n0 + nc;
+      const int kb = k0 + kr;
+      Bs[kr][nc] = (n < g.N && kb < k_end) ? g.B[(int64_t)kb * g.b_k + n * g.b_n] : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kTK; ks += 8) {
+      bf16x4 a, b;
+      const int kk = ks + (lane >> 5) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = (short)As[wm + (lane & 31)][kk + i];
+        b[i] = (short)Bs[kk + i][wn + (lane & 31)];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds column wn + lane%32, rows 8*(j/4) + 4*(lane/32) + j%4
+  const int64_t n = n0 + wn + (lane & 31);
+  if (n >= g.N) return;
+  const float bn = g.bias ? g.bias[n] : 0.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int64_t m = m0 + wm + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    if (m >= g.M) continue;
+    float v = acc[j] + bn;
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    const int64_t o = m * g.c_m + n * g.c_n;
+    if (split) {  // partial sums over a slice of k (bias, ReLU and masks not allowed)
+      atomicAdd(static_cast<float *>(g.C) + o, acc[j]);
+      continue;
+    }
+    if (g.mask && !(bf2f(g.mask[o]) > 0.f)) v = 0.f;
+    if (g.out_bf16)
+      static_cast<uint16_t *>(g.C)[o] = f2bf(v);
+    else if (g.accumulate)
+      static_cast<float *>(g.C)[o] += v;
+    else
+      static_cast<float *>(g.C)[o] = v;
+  }
+}
+
+__global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0.f;
+}
+
+// Plain launch, or split-K (fp32 output zeroed first, partial sums added
+// atomically) when the output is small and K long: weight gradients.
+static void gemm(GemmArgs g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return;
+  const int64_t tiles = (int64_t)((g.M + kTM - 1) / kTM) * ((g.N + kTN - 1) / kTN);
+  int splits = 1;
+  if (!g.out_bf16 && !g.bias && !g.relu && !g.mask && !g.accumulate && tiles < 256 && g.K >= 8192)
+    splits = (int)std::min<int64_t>(std::max<int64_t>(1, 1024 / tiles), g.K / 4096);
+  dim3 grid((unsigned)((g.M + kTM - 1) / kTM), (unsigned)((g.N + kTN - 1) / kTN), (unsigned)splits);
+  if (splits > 1) {
+    g.k_chunk = (g.K + splits - 1) / splits;
+    g.k_chunk = (g.k_chunk + kTK - 1) / kTK * kTK;
+    // zero the (strided) fp32 output: M x N with strides c_m, c_n (dense here)
+    const int64_t span = (int64_t)(g.M - 1) * g.c_m + (int64_t)(g.N - 1) * g.c_n + 1;
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(span)), dim3(256), 0, st, static_cast<float *>(g.C), span);
+  } else {
+    g.k_chunk = g.K;
+  }
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+  check_hip(hipGetLastError(), "launch gemm");
+}
+
+// ---------------------------------------------------------------------------
+// im2col / col2im (3x3, padding 1, stride 1)
+// col[(n*H + h)*W + w][tap*C + c] = x(n, c, h+dh, w+dw), tap = (dh+1)*3 + (dw+1)
+// x addressed with strides (n, c, h, w) so both NCHW inputs and NHWC
+// activations are read in place.
+// ---------------------------------------------------------------------------
+__global__ void k_im2col(const uint16_t *__restrict__ x, int64_t sn, int64_t sc, int64_t sh, int64_t sw, int N,
+                         int C, int H, int W, uint16_t *__restrict__ col) {
+  const int64_t total = (int64_t)N * H * W * 9 * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int tap = (int)((i / C) % 9);
+    const int64_t p = i / (9 * (int64_t)C);
+    const int w = (int)(p % W), h = (int)((p / W) % H);
+    const int n = (int)(p / ((int64_t)W * H));
+    const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
+    col[i] = (hh >= 0 && hh < H && ww >= 0 && ww < W) ? x[n * sn + c * sc + hh * sh + ww * sw] : (uint16_t)0;
+  }
+}
+
+// dx(n, h, w, c) = sum over taps of dcol[pixel (h - dh, w - dw)][tap*C + c], NHWC bf16 output
+__global__ void k_col2im(const uint16_t *__restrict__ dcol, int N, int C, int H, int W, uint16_t *__restrict__ dx) {
+  const int64_t total = (int64_t)N * H * W * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int w = (int)(p % W), h = (int)((p / W) % H);
+    const int n = (int)(p / ((int64_t)W * H));
+    float s = 0.f;
+    for (int tap = 0; tap < 9; ++tap) {
+      const int hh = h - (tap / 3 - 1), ww = w - (tap % 3 - 1);
+      if (hh < 0 || hh >= H || ww < 0 || ww >= W) continue;
+      s += bf2f(dcol[(((int64_t)n * H + hh) * W + ww) * 9 * C + tap * C + c]);
+    }
+    dx[i] = f2bf(s);
+  }
+}
+
+// 2x2 max-pool (NHWC); idx = position of the maximum (first on ties)
+__global__ void k_pool_fwd(const uint16_t *__restrict__ x, int N, int C, int H, int W, uint16_t *__restrict__ y,
+                           uint8_t *__restrict__ idx) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t total = (int64_t)N * Ho * Wo * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int w = (int)(p % Wo), h = (int)((p / Wo) % Ho);
+    const int n = (int)(p / ((int64_t)Wo * Ho));
+    float best = -INFINITY;
+    int bi = 0;
+    for (int q = 0; q < 4; ++q) {
+      const float v = bf2f(x[(((int64_t)n * H + 2 * h + q / 2) * W + 2 * w + q % 2) * C + c]);
+      if (v > best) {
+        best = v;
+        bi = q;
+      }
+    }
+    y[i] = f2bf(best);
+    idx[i] = (uint8_t)bi;
+  }
+}
+
+// d(pre-activation) of the conv output: route dy to the pooled position,
+// times the ReLU derivative (activation > 0).  dy may be fp32 or bf16 (NHWC
+// of the pooled shape); output bf16 NHWC of the full shape.
+__global__ void k_pool_bwd(const uint16_t *__restrict__ dy, const uint8_t *__restrict__ idx,
+                           const uint16_t *__restrict__ act, int N, int C, int H, int W, uint16_t *__restrict__ dpre) {
+  const int64_t total = (int64_t)N * H * W * C;
+  const int Ho = H / 2, Wo = W / 2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int w = (int)(p % W), h = (int)((p / W) % H);
+    const int n = (int)(p / ((int64_t)W * H));
+    const int64_t o = (((int64_t)n * Ho + h / 2) * Wo + w / 2) * C + c;
+    const int q = (h & 1) * 2 + (w & 1);
+    float g = 0.f;
+    if (idx[o] == q && bf2f(act[i]) > 0.f) g = bf2f(dy[o]);
+    dpre[i] = f2bf(g);
+  }
+}
+
+// BCE with logits: per-sample loss and dz = (sigmoid(z) - y) / n (bf16 for the GEMMs)
+__global__ void k_bce(const float *__restrict__ z, const float *__restrict__ y, int n, float *__restrict__ loss,
+                      uint16_t *__restrict__ dz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float zi = z[i], yi = y[i];
+  loss[i] = fmaxf(zi, 0.f) - zi * yi + log1pf(expf(-fabsf(zi)));
+  const float s = 1.f / (1.f + expf(-zi));
+  dz[i] = f2bf((s - yi) / (float)n);
+}
+
+// Adam on fp32 master parameters; refreshes the bf16 copy
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, uint16_t *__restrict__ pb, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float upd = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] -= upd;
+    pb[i] = f2bf(p[i]);
+  }
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, uint16_t *__restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = f2bf(a[i]);
+}
+
+__global__ void k_fill_bf16(uint16_t *__restrict__ a, int64_t n, uint16_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Cutouts (a candidate's DM-time and frequency-time images)
+// ---------------------------------------------------------------------------
+struct CutRow {
+  const int32_t *dmt;     // row block of the plan output, [n_dm][n_out]
+  const int32_t *delays;  // int32 [n_dm][nchan]
+  int64_t n_out;
+  int32_t n_dm, D, trial0;
+};
+struct CutoutArgs {
+  const uint8_t *fb;  // uint8 [nsamp][nchan]
+  const double *musig;
+  const gsp_candidate *cand;
+  int64_t n;
+  int32_t nchan, n_seg, rmax;
+  CutRow row[GSP_MAX_SEG];
+  uint16_t *out;  // bf16 [n][2][64][64]
+};
+
+// One workgroup per candidate.  Box end e = t_peak + width - 1 (row
+// resolution), bin width r = clamp(width / 8, 1, rmax); bin b covers samples
+// e - (64 - b) r + 1 .. e - (63 - b) r, so the box fills the last ~8 bins and
+// nothing after e is used.
+//  image 0 (DM-time): 64 trials centred on the candidate's (clamped to the
+//    row), bin sums of the dedispersed series; samples before the start
+//    count as the trial's mean;
+//  image 1 (frequency-time): 64 sub-bands of nchan/64 channels, each channel
+//    shifted by its delay at the candidate's DM, bin sums of the raw
+//    samples; a bin partly before the start is scaled up to r samples, one
+//    wholly before it takes its band's mean.
+// Each image is then z-scored (zero mean, unit variance; constant -> 0).
+__global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
+  __shared__ float img[2][64 * 64];
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t k = blockIdx.x; k < a.n; k += gridDim.x) {
+    const gsp_candidate c = a.cand[k];
+    const CutRow R = a.row[c.seg];
+    const int64_t e = c.t_peak + c.width - 1;
+    const int r = max(1, min(a.rmax, c.width / 8));
+    const int lo = max(0, min(c.dm_index - 32, R.n_dm - 64));
+    // ---- DM-time ----
+    for (int u = tid; u < 64 * 64; u += 256) {
+      const int q = u / 64, b = u % 64;
+      const int tr = lo + q;
+      float v = 0.f;
+      if (tr < R.n_dm) {
+        const int32_t *x = R.dmt + (int64_t)tr * R.n_out;
+        const double mu = a.musig[2 * (R.trial0 + tr)];
+        double sacc = 0.0;
+        const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
+        for (int j = 0; j < r; ++j) {
+          const int64_t t = t0 + j;
+          sacc += t >= 0 ? (double)x[t] : mu;
+        }
+        v = (float)sacc;
+      }
+      img[0][u] = v;
+    }
+    // ---- frequency-time: one wave per band, lanes over the band's channels ----
+    const int dmi = c.dm_index;
+    for (int band = wave; band < 64; band += 4) {
+      const int cb = (int)((int64_t)band * a.nchan / 64), ce = (int)((int64_t)(band + 1) * a.nchan / 64);
+      double valid_sum = 0.0;
+      int n_valid_bins = 0;
+      for (int b = 0; b < 64; ++b) {
+        const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
+        double acc = 0.0;
+        int cnt = 0;
+        for (int ch = cb + lane; ch < ce; ch += 64) {
+          const int64_t d = R.delays[(int64_t)dmi * a.nchan + ch];
+          for (int j = 0; j < r; ++j) {
+            const int64_t t = t0 + j;
+            if (t < 0) continue;
+            const uint8_t *p = a.fb + ((t + d) * R.D) * (int64_t)a.nchan + ch;
+            for (int m = 0; m < R.D; ++m) acc += p[(int64_t)m * a.nchan];
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        const int64_t first = max((int64_t)0, t0);
+        cnt = (int)max((int64_t)0, t0 + r - first);
+        float v = cnt > 0 ? (float)(acc * (double)r / (double)cnt) : NAN;
+        if (cnt > 0) {
+          valid_sum += v;
+          ++n_valid_bins;
+        }
+        if (lane == 0) img[1][band * 64 + b] = v;
+      }
+      if (lane == 0 && n_valid_bins < 64) {
+        const float fill = n_valid_bins ? (float)(valid_sum / n_valid_bins) : 0.f;
+        for (int b = 0; b < 64; ++b)
+          if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
+      }
+    }
+    __syncthreads();
+    // ---- z-score each image ----
+    for (int im = 0; im < 2; ++im) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int u = tid; u < 4096; u += 256) {
+        const double v = img[im][u];
+        s1 += v;
+        s2 += v * v;
+      }
+      red[0][tid] = s1;
+      red[1][tid] = s2;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+          red[0][tid] += red[0][tid + h];
+          red[1][tid] += red[1][tid + h];
+        }
+        __syncthreads();
+      }
+      const double mean = red[0][0] / 4096.0;
+      const double var = red[1][0] / 4096.0 - mean * mean;
+      const double inv = var > 1e-12 * (mean * mean + 1.0) ? 1.0 / sqrt(var) : 0.0;
+      uint16_t *o = a.out + ((int64_t)k * 2 + im) * 4096;
+      for (int u = tid; u < 4096; u += 256) o[u] = f2bf((float)(((double)img[im][u] - mean) * inv));
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the network
+// ---------------------------------------------------------------------------
+struct ConvSpec {
+  int cin, cout, h;  // input channels, output channels, input height = width
+};
+static const ConvSpec kConv[4] = {{2, 16, 64}, {16, 32, 32}, {32, 64, 16}, {64, 128, 8}};
+static constexpr int kFlat = 128 * 4 * 4, kHidden = 192;
+
+struct ParamLayout {
+  int64_t w[6], b[6];  // offsets (conv1..4, fc1, fc2)
+  int64_t wn[6], bn[6];
+  int64_t total;
+};
+
+static ParamLayout layout() {
+  ParamLayout L;
+  int64_t o = 0;
+  for (int l = 0; l < 6; ++l) {
+    int64_t wn, bn;
+    if (l < 4) {
+      wn = (int64_t)kConv[l].cout * 9 * kConv[l].cin;
+      bn = kConv[l].cout;
+    } else if (l == 4) {
+      wn = (int64_t)kHidden * kFlat;
+      bn = kHidden;
+    } else {
+      wn = kHidden;
+      bn = 1;
+    }
+    L.w[l] = o;
+    L.wn[l] = wn;
+    o += wn;
+    L.b[l] = o;
+    L.bn[l] = bn;
+    o += bn;
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace gsp
+
+using namespace gsp;
+
+struct gsp_cnn {
+  gsp_ctx *ctx = nullptr;
+  ParamLayout L;
+  DevBuf p32, pbf, g32, m, v, ones;
+  int64_t t = 0;  // Adam steps
+  // activations and scratch for batches up to `cap`
+  int64_t cap = 0;
+  int64_t last_n = 0;  // batch of the last forward pass
+  DevBuf col[4], act[4], pool[4], idx[4], h1, z, dz, loss, dh1, dp4, dcol, dpre, dpool;
+};
+
+namespace {
+
+void reserve_batch(gsp_cnn *c, int64_t n) {
+  if (n <= c->cap) return;
+  const int dev = c->ctx->device;
+  for (int l = 0; l < 4; ++l) {
+    const int64_t px = n * kConv[l].h * kConv[l].h;
+    c->col[l].device = dev;
+    c->col[l].reserve((size_t)px * 9 * kConv[l].cin * 2);
+    c->act[l].device = dev;
+    c->act[l].reserve((size_t)px * kConv[l].cout * 2);
+    c->pool[l].device = dev;
+    c->pool[l].reserve((size_t)px / 4 * kConv[l].cout * 2);
+    c->idx[l].device = dev;
+    c->idx[l].reserve((size_t)px / 4 * kConv[l].cout);
+  }
+  int64_t big = 0;
+  for (int l = 0; l < 4; ++l) big = std::max<int64_t>(big, n * kConv[l].h * kConv[l].h * 9 * kConv[l].cin);
+  for (DevBuf *d : {&c->h1, &c->z, &c->dz, &c->loss, &c->dh1, &c->dp4, &c->dcol, &c->dpre, &c->dpool, &c->ones})
+    d->device = dev;
+  c->h1.reserve((size_t)n * kHidden * 2);
+  c->z.reserve((size_t)n * 4);
+  c->dz.reserve((size_t)n * 2);
+  c->loss.reserve((size_t)n * 4);
+  c->dh1.reserve((size_t)n * kHidden * 2);
+  c->dp4.reserve((size_t)n * kFlat * 2);
+  c->dcol.reserve((size_t)big * 2);
+  c->dpre.reserve((size_t)n * 64 * 64 * 16 * 2);
+  c->dpool.reserve((size_t)n * 32 * 32 * 16 * 2);
+  c->ones.reserve((size_t)n * 64 * 64 * 2);
+  hipLaunchKernelGGL(k_fill_bf16, dim3(grid_for(n * 4096)), dim3(256), 0, 0, c->ones.as<uint16_t>(), n * 4096,
+                     (uint16_t)0x3F80);
+  check_hip(hipDeviceSynchronize(), "fill ones");
+  c->cap = n;
+}
+
+GemmArgs ga(const uint16_t *A, int64_t am, int64_t ak, const uint16_t *B, int64_t bk, int64_t bn, void *C, int64_t cm,
+            int64_t cn, int64_t M, int64_t N, int64_t K) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A;
+  g.a_m = am;
+  g.a_k = ak;
+  g.B = B;
+  g.b_k = bk;
+  g.b_n = bn;
+  g.C = C;
+  g.c_m = cm;
+  g.c_n = cn;
+  g.M = (int32_t)M;
+  g.N = (int32_t)N;
+  g.K = (int32_t)K;
+  return g;
+}
+
+// Forward pass of a batch; logits (fp32) left in c->z.
+void forward(gsp_cnn *c, const uint16_t *x, int64_t n, hipStream_t st) {
+  const uint16_t *wb = c->pbf.as<uint16_t>();
+  const float *p = c->p32.as<float>();
+  const uint16_t *in = x;
+  int64_t sn = 2 * 64 * 64, sc = 64 * 64, sh = 64, sw = 1;  // NCHW input
+  for (int l = 0; l < 4; ++l) {
+    const ConvSpec &cs = kConv[l];
+    const int H = cs.h;
+    const int64_t M = n * H * H, K = 9 * cs.cin;
+    hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, in, sn, sc, sh, sw, (int)n, cs.cin, H, H,
+                       c->col[l].as<uint16_t>());
+    GemmArgs g = ga(c->col[l].as<uint16_t>(), K, 1, wb + c->L.w[l], 1, K, c->act[l].ptr, cs.cout, 1, M, cs.cout, K);
+    g.bias = p + c->L.b[l];
+    g.relu = 1;
+    g.out_bf16 = 1;
+    gemm(g, st);
+    hipLaunchKernelGGL(k_pool_fwd, dim3(grid_for(M / 4 * cs.cout)), dim3(256), 0, st, c->act[l].as<uint16_t>(),
+                       (int)n, cs.cout, H, H, c->pool[l].as<uint16_t>(), c->idx[l].as<uint8_t>());
+    in = c->pool[l].as<uint16_t>();
+    const int Ho = H / 2;
+    sn = (int64_t)Ho * Ho * cs.cout;
+    sc = 1;
+    sh = (int64_t)Ho * cs.cout;
+    sw = cs.cout;
+  }
+  // fc1 (+ReLU) and fc2
+  GemmArgs g1 = ga(c->pool[3].as<uint16_t>(), kFlat, 1, wb + c->L.w[4], 1, kFlat, c->h1.ptr, kHidden, 1, n, kHidden,
+                   kFlat);
+  g1.bias = p + c->L.b[4];
+  g1.relu = 1;
+  g1.out_bf16 = 1;
+  gemm(g1, st);
+  GemmArgs g2 = ga(c->h1.as<uint16_t>(), kHidden, 1, wb + c->L.w[5], 1, kHidden, c->z.ptr, 1, 1, n, 1, kHidden);
+  g2.bias = p + c->L.b[5];
+  gemm(g2, st);
+}
+
+// Backward pass after forward(): gradients (fp32) of the mean BCE into c->g32.
+void backward(gsp_cnn *c, const float *labels, int64_t n, hipStream_t st) {
+  const uint16_t *wb = c->pbf.as<uint16_t>();
+  float *g = c->g32.as<float>();
+  const uint16_t *ones = c->ones.as<uint16_t>();
+  hipLaunchKernelGGL(k_bce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->z.as<float>(), labels, (int)n,
+                     c->loss.as<float>(), c->dz.as<uint16_t>());
+  const uint16_t *dz = c->dz.as<uint16_t>();
+  // fc2: dW = dz^T h1, db = sum dz, dh1 = dz W2 masked by ReLU
+  gemm(ga(dz, 0, 1, c->h1.as<uint16_t>(), kHidden, 1, g + c->L.w[5], 1, 1, 1, kHidden, n), st);
+  gemm(ga(ones, 0, 0, dz, 1, 0, g + c->L.b[5], 1, 1, 1, 1, n), st);
+  GemmArgs gh = ga(dz, 1, 0, wb + c->L.w[5], 0, 1, c->dh1.ptr, kHidden, 1, n, kHidden, 1);
+  gh.mask = c->h1.as<uint16_t>();
+  gh.out_bf16 = 1;
+  gemm(gh, st);
+  const uint16_t *dh = c->dh1.as<uint16_t>();
+  // fc1: dW = dh^T x, db = colsum dh, dx = dh W1
+  gemm(ga(dh, 1, kHidden, c->pool[3].as<uint16_t>(), kFlat, 1, g + c->L.w[4], kFlat, 1, kHidden, kFlat, n), st);
+  gemm(ga(ones, 0, 0, dh, kHidden, 1, g + c->L.b[4], 1, 1, 1, kHidden, n), st);
+  GemmArgs gx = ga(dh, kHidden, 1, wb + c->L.w[4], kFlat, 1, c->dp4.ptr, kFlat, 1, n, kFlat, kHidden);
+  gx.out_bf16 = 1;
+  gemm(gx, st);
+  const uint16_t *dy = c->dp4.as<uint16_t>();  // gradient of the pooled output of conv l
+  for (int l = 3; l >= 0; --l) {
+    const ConvSpec &cs = kConv[l];
+    const int H = cs.h;
+    const int64_t M = n * H * H, K = 9 * cs.cin;
+    uint16_t *dpre = c->dpre.as<uint16_t>();
+    hipLaunchKernelGGL(k_pool_bwd, dim3(grid_for(M * cs.cout)), dim3(256), 0, st, dy, c->idx[l].as<uint8_t>(),
+                       c->act[l].as<uint16_t>(), (int)n, cs.cout, H, H, dpre);
+    // dW[o][k] = sum_p dpre[p][o] col[p][k]; db[o] = sum_p dpre[p][o]
+    gemm(ga(dpre, 1, cs.cout, c->col[l].as<uint16_t>(), K, 1, g + c->L.w[l], K, 1, cs.cout, K, M), st);
+    gemm(ga(ones, 0, 0, dpre, cs.cout, 1, g + c->L.b[l], 1, 1, 1, cs.cout, M), st);
+    if (l == 0) break;
+    // dcol = dpre W; dx = col2im(dcol) (NHWC of the previous pooled output)
+    GemmArgs gc = ga(dpre, cs.cout, 1, wb + c->L.w[l], K, 1, c->dcol.ptr, K, 1, M, K, cs.cout);
+    gc.out_bf16 = 1;
+    gemm(gc, st);
+    hipLaunchKernelGGL(k_col2im, dim3(grid_for(M * cs.cin)), dim3(256), 0, st, c->dcol.as<uint16_t>(), (int)n, cs.cin,
+                       H, H, c->dpool.as<uint16_t>());
+    // the dpool buffer is consumed by the next layer's pool_bwd before being rewritten
+    dy = c->dpool.as<uint16_t>();
+  }
+}
+
+uint64_t splitmix64(uint64_t &s) {
+  // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014)
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void upload_params(gsp_cnn *c, const float *host) {
+  const int64_t n = c->L.total;
+  check_hip(hipMemcpy(c->p32.ptr, host, (size_t)n * 4, hipMemcpyHostToDevice), "copy parameters");
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, 0, c->p32.as<float>(), c->pbf.as<uint16_t>(), n);
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(n)), dim3(256), 0, 0, c->m.as<float>(), n);
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(n)), dim3(256), 0, 0, c->v.as<float>(), n);
+  check_hip(hipDeviceSynchronize(), "initialise parameters");
+  c->t = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t gsp_cnn_num_params(void) { return layout().total; }
+
+int gsp_cnn_create(gsp_ctx *ctx, uint64_t seed, gsp_cnn **out) {
+  if (!ctx || !out) return GSP_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    auto c = std::make_unique<gsp_cnn>();
+    c->ctx = ctx;
+    c->L = layout();
+    const int64_t n = c->L.total;
+    for (DevBuf *d : {&c->p32, &c->pbf, &c->g32, &c->m, &c->v}) d->device = ctx->device;
+    c->p32.reserve((size_t)n * 4);
+    c->pbf.reserve((size_t)n * 2);
+    c->g32.reserve((size_t)n * 4);
+    c->m.reserve((size_t)n * 4);
+    c->v.reserve((size_t)n * 4);
+    // He-uniform weights (fan-in), zero biases
+    std::vector<float> h((size_t)n, 0.f);
+    uint64_t st = seed;
+    for (int l = 0; l < 6; ++l) {
+      const double fan_in = l < 4 ? 9.0 * kConv[l].cin : (l == 4 ? (double)kFlat : (double)kHidden);
+      const double bound = std::sqrt(6.0 / fan_in);
+      for (int64_t i = 0; i < c->L.wn[l]; ++i) {
+        const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+        h[(size_t)(c->L.w[l] + i)] = (float)((2.0 * u - 1.0) * bound);
+      }
+    }
+    upload_params(c.get(), h.data());
+    *out = c.release();
+  });
+}
+
+void gsp_cnn_destroy(gsp_cnn *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->ctx->device);
+  (void)hipDeviceSynchronize();
+  delete c;
+}
+
+int gsp_cnn_get_params(gsp_cnn *c, float *host, int64_t n) {
+  if (!c || !host || n != c->L.total) return GSP_EINVAL;
+  return guarded(c->ctx, [&] {
+    check_hip(hipMemcpy(host, c->p32.ptr, (size_t)n * 4, hipMemcpyDeviceToHost), "copy parameters");
+  });
+}
+
+int gsp_cnn_set_params(gsp_cnn *c, const float *host, int64_t n) {
+  if (!c || !host || n != c->L.total) return GSP_EINVAL;
+  return guarded(c->ctx, [&] { upload_params(c, host); });
+}
+
+int gsp_cnn_save(const gsp_cnn *c, const char *path) {
+  if (!c || !path) return GSP_EINVAL;
+  std::vector<float> h((size_t)c->L.total);
+  if (hipMemcpy(h.data(), c->p32.ptr, h.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return GSP_EDEVICE;
+  std::ofstream f(path, std::ios::binary);
+  if (!f) return GSP_EINVAL;
+  const int64_t n = c->L.total;
+  f.write("GSPCNN01", 8);
+  f.write(reinterpret_cast<const char *>(&n), 8);
+  f.write(reinterpret_cast<const char *>(h.data()), (std::streamsize)(h.size() * 4));
+  return f.good() ? GSP_OK : GSP_EINVAL;
+}
+
+int gsp_cnn_load(gsp_cnn *c, const char *path) {
+  if (!c || !path) return GSP_EINVAL;
+  std::ifstream f(path, std::ios::binary);
+  char magic[8];
+  int64_t n = 0;
+  if (!f.read(magic, 8) || std::memcmp(magic, "GSPCNN01", 8) || !f.read(reinterpret_cast<char *>(&n), 8) ||
+      n != c->L.total)
+    return GSP_EINVAL;
+  std::vector<float> h((size_t)n);
+  if (!f.read(reinterpret_cast<char *>(h.data()), (std::streamsize)(n * 4))) return GSP_EINVAL;
+  return gsp_cnn_set_params(c, h.data(), n);
+}
+
+int gsp_cnn_forward(gsp_cnn *c, const uint16_t *x, int64_t n, float *logits, void *stream) {
+  if (!c) return GSP_EINVAL;
+  return guarded(c->ctx, [&] {
+    if (!x || !logits || n < 0) fail(GSP_EINVAL, "bad arguments");
+    if (n == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    reserve_batch(c, n);
+    forward(c, x, n, st);
+    c->last_n = n;
+    check_hip(hipMemcpyAsync(logits, c->z.ptr, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "copy logits");
+  });
+}
+
+int gsp_cnn_gradients(gsp_cnn *c, const uint16_t *x, const float *labels, int64_t n, float *grads_host,
+                      float *loss_host, void *stream) {
+  if (!c) return GSP_EINVAL;
+  return guarded(c->ctx, [&] {
+    if (!x || !labels || n < 1 || !grads_host) fail(GSP_EINVAL, "bad arguments");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    reserve_batch(c, n);
+    forward(c, x, n, st);
+    c->last_n = n;
+    backward(c, labels, n, st);
+    std::vector<float> loss((size_t)n);
+    check_hip(hipMemcpyAsync(loss.data(), c->loss.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, st), "copy loss");
+    check_hip(hipMemcpyAsync(grads_host, c->g32.ptr, (size_t)c->L.total * 4, hipMemcpyDeviceToHost, st),
+              "copy gradients");
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    if (loss_host) {
+      double s = 0;
+      for (float v : loss) s += v;
+      *loss_host = (float)(s / (double)n);
+    }
+  });
+}
+
+int gsp_cnn_train_step(gsp_cnn *c, const uint16_t *x, const float *labels, int64_t n, float lr, float *loss_host,
+                       void *stream) {
+  if (!c) return GSP_EINVAL;
+  return guarded(c->ctx, [&] {
+    if (!x || !labels || n < 1 || !(lr > 0)) fail(GSP_EINVAL, "bad arguments");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    reserve_batch(c, n);
+    forward(c, x, n, st);
+    c->last_n = n;
+    backward(c, labels, n, st);
+    c->t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)c->t), c2 = 1.f - std::pow(b2, (float)c->t);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(c->L.total)), dim3(256), 0, st, c->p32.as<float>(), c->g32.as<float>(),
+                       c->m.as<float>(), c->v.as<float>(), c->pbf.as<uint16_t>(), c->L.total, lr, b1, b2, 1e-8f, c1,
+                       c2);
+    check_hip(hipGetLastError(), "launch adam");
+    if (loss_host) {
+      std::vector<float> loss((size_t)n);
+      check_hip(hipMemcpyAsync(loss.data(), c->loss.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, st), "copy loss");
+      check_hip(hipStreamSynchronize(st), "synchronise stream");
+      double s = 0;
+      for (float v : loss) s += v;
+      *loss_host = (float)(s / (double)n);
+    }
+  });
+}
+
+int gsp_cnn_activation(gsp_cnn *c, int32_t which, void *host, int64_t bytes) {
+  if (!c) return GSP_EINVAL;
+  return guarded(c->ctx, [&] {
+    const int64_t n = c->last_n;
+    if (!host || which < 0 || which > 5 || n < 1) fail(GSP_EINVAL, "bad arguments or no forward pass yet");
+    const void *src;
+    int64_t want;
+    if (which < 4) {
+      const int h = kConv[which].h / 2;
+      want = n * h * h * kConv[which].cout * 2;
+      src = c->pool[which].ptr;
+    } else if (which == 4) {
+      want = n * kHidden * 2;
+      src = c->h1.ptr;
+    } else {
+      want = n * 4;
+      src = c->z.ptr;
+    }
+    if (bytes != want) fail(GSP_EINVAL, "size does not match the last batch");
+    check_hip(hipDeviceSynchronize(), "synchronise");
+    check_hip(hipMemcpy(host, src, (size_t)want, hipMemcpyDeviceToHost), "copy activation");
+  });
+}
+
+int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int32_t *dmt, const gsp_dmt_desc *desc,
+                const gsp_candidate *cands, int64_t n, uint16_t *out, void *stream) {
+  if (!ctx) return GSP_EINVAL;
+  return guarded(ctx, [&] {
+    validate_desc(desc);
+    if (!fb || !freqs || !dmt || (n > 0 && (!cands || !out)) || n < 0) fail(GSP_EINVAL, "bad arguments");
+    if (n == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_stats(ctx, dmt, desc, st);  // per-trial means for padding before the start
+    CutoutArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.fb = fb;
+    a.musig = ctx->stats.as<double>();
+    a.cand = cands;
+    a.n = n;
+    a.nchan = desc->nchan;
+    a.n_seg = desc->n_seg;
+    a.rmax = 8;
+    a.out = out;
+    for (int32_t s = 0; s < desc->n_seg; ++s) {
+      RowTables &rt = row_tables(ctx, desc, freqs, s);
+      if (!rt.delays_dev.ptr) {
+        rt.delays_dev.device = ctx->device;
+        rt.delays_dev.reserve(rt.delays_host.size() * 4);
+        check_hip(hipMemcpy(rt.delays_dev.ptr, rt.delays_host.data(), rt.delays_host.size() * 4,
+                            hipMemcpyHostToDevice),
+                  "copy delays");
+      }
+      a.row[s].dmt = dmt + desc->offset[s];
+      a.row[s].delays = rt.delays_dev.as<int32_t>();
+      a.row[s].n_out = desc->n_out[s];
+      a.row[s].n_dm = desc->seg[s].n_dm;
+      a.row[s].D = desc->seg[s].downsamp;
+      a.row[s].trial0 = desc->trial0[s];
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>(n, 256 * 8);
+    hipLaunchKernelGGL(k_cutout, dim3(grid), dim3(256), 0, st, a);
+    check_hip(hipGetLastError(), "launch cutouts");
+  });
+}
+
+}  // extern "C"

@@ -57,6 +57,7 @@ struct RowTables {
   int32_t row_dwords = 0;    // LDS dwords per staged copy of a channel
   DevBuf addr;               // uint32 [n_dm_pad][nchan]: LDS dword offset per (trial, channel)
   DevBuf dmin;               // int32 [n_tiles][nchan]: aligned first delay per DM tile
+  DevBuf delays_dev;         // int32 [n_dm][nchan] (cutouts)
   std::vector<int32_t> delays_host;  // int32 [n_dm][nchan]
 };
 
