@@ -216,7 +216,8 @@ int gsp_stream_flush(gsp_stream *s);
 int gsp_stream_poll(gsp_stream *s, gsp_stream_candidate *out, int64_t cap, int64_t *n);
 int gsp_stream_report(gsp_stream *s, gsp_stream_stats *out);
 /* The last step's window of row `seg`: host int32 [n_dm][*n_t], outputs
- * *t_first .. *t_first + *n_t - 1 (worker stopped). */
+ * *t_first .. *t_first + *n_t - 1 (worker stopped).  *t_first and *n_t are
+ * always set; GSP_ECAPACITY if host_out is NULL or cap < n_dm * *n_t. */
 int gsp_stream_window(gsp_stream *s, int32_t beam_id, int32_t seg, int32_t *host_out, int64_t cap, int64_t *t_first,
                       int64_t *n_t);
 /* Beam state (rings, look-back, counters) to/from host memory; restore into a
@@ -297,7 +298,8 @@ int gsp_profile_read(gsp_ctx *ctx, gsp_kernel_stat *out, int32_t cap, int32_t *n
  * constant image becomes 0) and stored as bf16 (round to nearest even).
  * fb_dev, freqs_mhz, dmt_dev, desc: as for gsp_dedisperse (dmt_dev is its
  * output for this filterbank).  cands_dev: device gsp_candidate[n] (as
- * returned by the search, copied to the device).  out_dev: device
+ * returned by the search, copied to the device); a candidate whose row,
+ * trial or box end lies outside the plan gets two zero images.  out_dev: device
  * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`. */
 int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const int32_t *dmt_dev,
                 const gsp_dmt_desc *desc, const gsp_candidate *cands_dev, int64_t n, uint16_t *out_dev,

@@ -29,6 +29,14 @@ __host__ __device__ inline uint16_t f2bf(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+// double -> bf16 rounded once, to nearest even at 8 significant bits
+// (bf16 subnormals: multiples of 2^-133); finite inputs below bf16's range
+__device__ inline uint16_t d2bf(double x) {
+  int e;
+  const double m = frexp(x, &e);  // x = m 2^e, 0.5 <= |m| < 1
+  const double q = e >= -125 ? ldexp(rint(ldexp(m, 8)), e - 8) : ldexp(rint(ldexp(x, 133)), -133);
+  return f2bf((float)q);  // exact: q has at most 8 significant bits
+}
 __host__ __device__ inline float bf2f(uint16_t h) {
   uint32_t u = (uint32_t)h << 16;
   return __builtin_bit_cast(float, u);
@@ -305,11 +313,18 @@ struct CutoutArgs {
 //    wholly before it takes its band's mean.
 // Each image is then z-scored (zero mean, unit variance; constant -> 0).
 __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
-  __shared__ float img[2][64 * 64];
-  __shared__ double red[2][256];
+  __shared__ double img[2][64 * 64];
+  __shared__ double red[3][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t k = blockIdx.x; k < a.n; k += gridDim.x) {
     const gsp_candidate c = a.cand[k];
+    const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
+                    c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
+                    c.t_peak + c.width - 1 < a.row[c.seg].n_out;
+    if (!ok) {  // out of range for this plan: two zero images, nothing read
+      for (int u = tid; u < 2 * 4096; u += 256) a.out[(int64_t)k * 2 * 4096 + u] = 0;
+      continue;
+    }
     const CutRow R = a.row[c.seg];
     const int64_t e = c.t_peak + c.width - 1;
     const int r = max(1, min(a.rmax, c.width / 8));
@@ -318,7 +333,7 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
     for (int u = tid; u < 64 * 64; u += 256) {
       const int q = u / 64, b = u % 64;
       const int tr = lo + q;
-      float v = 0.f;
+      double v = 0.0;
       if (tr < R.n_dm) {
         const int32_t *x = R.dmt + (int64_t)tr * R.n_out;
         const double mu = a.musig[2 * (R.trial0 + tr)];
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
           const int64_t t = t0 + j;
           sacc += t >= 0 ? (double)x[t] : mu;
         }
-        v = (float)sacc;
+        v = sacc;
       }
       img[0][u] = v;
     }
@@ -354,7 +369,7 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         const int64_t first = max((int64_t)0, t0);
         cnt = (int)max((int64_t)0, t0 + r - first);
-        float v = cnt > 0 ? (float)(acc * (double)r / (double)cnt) : NAN;
+        const double v = cnt > 0 ? acc * (double)r / (double)cnt : NAN;
         if (cnt > 0) {
           valid_sum += v;
           ++n_valid_bins;
@@ -362,35 +377,50 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
         if (lane == 0) img[1][band * 64 + b] = v;
       }
       if (lane == 0 && n_valid_bins < 64) {
-        const float fill = n_valid_bins ? (float)(valid_sum / n_valid_bins) : 0.f;
+        const double fill = n_valid_bins ? valid_sum / n_valid_bins : 0.0;
         for (int b = 0; b < 64; ++b)
           if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
       }
     }
     __syncthreads();
-    // ---- z-score each image ----
+    // ---- z-score each image (two passes; an image of equal pixels becomes 0) ----
     for (int im = 0; im < 2; ++im) {
-      double s1 = 0.0, s2 = 0.0;
+      double s1 = 0.0, vmin = INFINITY, vmax = -INFINITY;
       for (int u = tid; u < 4096; u += 256) {
         const double v = img[im][u];
         s1 += v;
-        s2 += v * v;
+        vmin = fmin(vmin, v);
+        vmax = fmax(vmax, v);
       }
       red[0][tid] = s1;
-      red[1][tid] = s2;
+      red[1][tid] = vmin;
+      red[2][tid] = vmax;
       __syncthreads();
       for (int h = 128; h > 0; h >>= 1) {
         if (tid < h) {
           red[0][tid] += red[0][tid + h];
-          red[1][tid] += red[1][tid + h];
+          red[1][tid] = fmin(red[1][tid], red[1][tid + h]);
+          red[2][tid] = fmax(red[2][tid], red[2][tid + h]);
         }
         __syncthreads();
       }
       const double mean = red[0][0] / 4096.0;
-      const double var = red[1][0] / 4096.0 - mean * mean;
-      const double inv = var > 1e-12 * (mean * mean + 1.0) ? 1.0 / sqrt(var) : 0.0;
+      const bool flat = red[1][0] == red[2][0];
+      __syncthreads();
+      double s2 = 0.0;
+      for (int u = tid; u < 4096; u += 256) {
+        const double d = img[im][u] - mean;
+        s2 += d * d;
+      }
+      red[0][tid] = s2;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[0][tid] += red[0][tid + h];
+        __syncthreads();
+      }
+      const double inv = flat ? 0.0 : 1.0 / sqrt(red[0][0] / 4096.0);
       uint16_t *o = a.out + ((int64_t)k * 2 + im) * 4096;
-      for (int u = tid; u < 4096; u += 256) o[u] = f2bf((float)(((double)img[im][u] - mean) * inv));
+      for (int u = tid; u < 4096; u += 256) o[u] = d2bf((img[im][u] - mean) * inv);
       __syncthreads();
     }
   }

@@ -415,7 +415,9 @@ class Stream:
         """(t_first, int32 [n_dm][n_t]) of the last step's window of a row."""
         t0 = C.c_int64()
         nt = C.c_int64()
-        self._check(_L.gsp_stream_window(self.h, int(beam), int(seg), None, 0, C.byref(t0), C.byref(nt)))
+        st = _L.gsp_stream_window(self.h, int(beam), int(seg), None, 0, C.byref(t0), C.byref(nt))
+        if st not in (GSP_OK, GSP_ECAPACITY):
+            self._check(st)
         out = np.empty((n_dm, nt.value), np.int32)
         if nt.value > 0:
             self._check(_L.gsp_stream_window(self.h, int(beam), int(seg), out.ctypes.data, out.size, C.byref(t0),
@@ -433,3 +435,136 @@ class Stream:
 
     def restore(self, beam: int, data: bytes):
         self._check(_L.gsp_stream_restore(self.h, int(beam), data, len(data)))
+
+
+# --- learned triage ------------------------------------------------------------
+_L.gsp_cutouts.argtypes = [P, P, P, P, C.POINTER(DmtDesc), P, C.c_int64, P, P]
+_L.gsp_cutouts.restype = C.c_int
+_L.gsp_cnn_num_params.argtypes = []
+_L.gsp_cnn_num_params.restype = C.c_int64
+_L.gsp_cnn_create.argtypes = [P, C.c_uint64, C.POINTER(P)]
+_L.gsp_cnn_create.restype = C.c_int
+_L.gsp_cnn_destroy.argtypes = [P]
+_L.gsp_cnn_destroy.restype = None
+for _n in ("gsp_cnn_get_params", "gsp_cnn_set_params"):
+    getattr(_L, _n).argtypes = [P, P, C.c_int64]
+    getattr(_L, _n).restype = C.c_int
+for _n in ("gsp_cnn_save", "gsp_cnn_load"):
+    getattr(_L, _n).argtypes = [P, C.c_char_p]
+    getattr(_L, _n).restype = C.c_int
+_L.gsp_cnn_forward.argtypes = [P, P, C.c_int64, P, P]
+_L.gsp_cnn_forward.restype = C.c_int
+_L.gsp_cnn_gradients.argtypes = [P, P, P, C.c_int64, P, P, P]
+_L.gsp_cnn_gradients.restype = C.c_int
+_L.gsp_cnn_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, P, P]
+_L.gsp_cnn_train_step.restype = C.c_int
+_L.gsp_cnn_activation.argtypes = [P, C.c_int32, P, C.c_int64]
+_L.gsp_cnn_activation.restype = C.c_int
+
+
+def cutouts(ctx: Context, fb, freqs, dmt, desc: DmtDesc, cands: np.ndarray, out=None, stream=None):
+    """bf16 (torch.int16 storage of the bit patterns) [n][2][64][64] cutouts
+    of candidates (CAND_DTYPE, host) on the device."""
+    import torch
+    n = len(cands)
+    if out is None:
+        out = torch.empty((n, 2, 64, 64), dtype=torch.int16, device=fb.device)
+    if n == 0:
+        return out
+    c = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    cd = torch.from_numpy(c.view(np.uint8).copy()).to(fb.device)
+    f = _f64(freqs)
+    _check(_L.gsp_cutouts(ctx.h, C.c_void_p(fb.data_ptr()), f.ctypes.data, C.c_void_p(dmt.data_ptr()),
+                          C.byref(desc), C.c_void_p(cd.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                          _stream_handle(stream)), ctx.h)
+    if stream is None:
+        torch.cuda.current_stream().synchronize()  # keep `cd` alive until the kernel has read it
+    else:
+        stream.synchronize()
+    return out
+
+
+class Cnn:
+    """Triage network on the device (parameters as one float vector, in the
+    library's documented order)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        self.h = P()
+        _check(_L.gsp_cnn_create(ctx.h, C.c_uint64(seed), C.byref(self.h)), ctx.h)
+        self.n_params = int(_L.gsp_cnn_num_params())
+
+    def close(self):
+        if self.h:
+            _L.gsp_cnn_destroy(self.h)
+            self.h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(_L.gsp_cnn_get_params(self.h, out.ctypes.data, self.n_params), self.ctx.h)
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.n_params
+        _check(_L.gsp_cnn_set_params(self.h, p.ctypes.data, self.n_params), self.ctx.h)
+
+    def save(self, path: str):
+        _check(_L.gsp_cnn_save(self.h, path.encode()), self.ctx.h)
+
+    def load(self, path: str):
+        _check(_L.gsp_cnn_load(self.h, path.encode()), self.ctx.h)
+
+    @staticmethod
+    def _x(x):
+        import torch
+        assert x.is_cuda and x.is_contiguous() and x.dtype in (torch.int16, torch.bfloat16)
+        assert tuple(x.shape[1:]) == (2, 64, 64)
+        return C.c_void_p(x.data_ptr()), int(x.shape[0])
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        xp, n = self._x(x)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(_L.gsp_cnn_forward(self.h, xp, n, C.c_void_p(out.data_ptr()), _stream_handle(stream)), self.ctx.h)
+        return out
+
+    def gradients(self, x, labels, stream=None):
+        xp, n = self._x(x)
+        assert labels.is_cuda and labels.numel() == n
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_float()
+        _check(_L.gsp_cnn_gradients(self.h, xp, C.c_void_p(labels.data_ptr()), n, g.ctypes.data, C.byref(loss),
+                                    _stream_handle(stream)), self.ctx.h)
+        return g, float(loss.value)
+
+    def train_step(self, x, labels, lr: float, want_loss: bool = True, stream=None):
+        xp, n = self._x(x)
+        assert labels.is_cuda and labels.numel() == n
+        loss = C.c_float()
+        _check(_L.gsp_cnn_train_step(self.h, xp, C.c_void_p(labels.data_ptr()), n, float(lr),
+                                     C.byref(loss) if want_loss else None, _stream_handle(stream)), self.ctx.h)
+        return float(loss.value) if want_loss else None
+
+    def activation(self, which: int, n: int) -> np.ndarray:
+        """Stored activation of the last forward pass (bf16 values as float64
+        for which < 5, float32 logits for 5)."""
+        if which < 4:
+            h = 32 >> which
+            shape, dt = (n, h, h, 16 << which), np.uint16
+        elif which == 4:
+            shape, dt = (n, 192), np.uint16
+        else:
+            shape, dt = (n,), np.float32
+        out = np.empty(shape, dt)
+        _check(_L.gsp_cnn_activation(self.h, int(which), out.ctypes.data, out.nbytes), self.ctx.h)
+        if dt == np.uint16:
+            return (out.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        return out

@@ -1,0 +1,251 @@
+"""Triage network and cutouts on the GPU against the CPU oracle (oracle/cnn.py).
+
+Per layer, the oracle is fed the GPU's own bf16 input to that layer, so a
+difference can only come from the layer itself: float32 vs float64
+accumulation moves a stored bf16 value by at most one rounding step.  End to
+end (logits, gradients) the oracle starts from the same bf16 input and
+parameters, and rounding steps that fall differently propagate; the bound
+there is looser and stated per test."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from paper_2110_12749_amd import synth
+from tests._util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(dev):
+    import torch
+    from paper_2110_12749_amd import gsp
+    ctx = gsp.Context(0)
+    yield gsp, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def to_dev(torch, x):
+    """float64 values -> bf16 bit patterns on the device (torch.int16)."""
+    return torch.from_numpy(ocnn.bf16_bits(x).view(np.int16)).to("cuda:0")
+
+
+def inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    x = ocnn.bf16(rng.normal(size=(n, 2, 64, 64)))
+    y = (rng.random(n) < 0.5).astype(np.float64)
+    return x, y
+
+
+def close_bf16(gpu, ora, what):
+    """bf16-stored values: equal up to one rounding step (relative 2^-7 of the
+    larger magnitude, or a tiny absolute amount near 0), mostly identical."""
+    scale = np.abs(ora).max() + 1e-30
+    diff = np.abs(gpu - ora)
+    bound = 2.0 ** -7 * np.maximum(np.abs(gpu), np.abs(ora)) + 1e-5 * scale
+    bad = diff > bound
+    same = np.mean(gpu == ora)
+    say(f"  {what}: identical {same:.5f}, max rel diff {np.max(diff / (np.abs(ora) + 1e-3 * scale)):.2e}")
+    assert not bad.any(), (what, np.argwhere(bad)[:5], gpu[bad][:5], ora[bad][:5])
+    assert same >= 0.98, (what, same)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30))
+
+
+def test_forward_layer_by_layer(env):
+    gsp, ctx, torch = env
+    net = gsp.Cnn(ctx, seed=3)
+    p = net.params().astype(np.float64)
+    P = {k: (ocnn.bf16(v) if k.endswith(".w") else v) for k, v in ocnn.unpack(p).items()}
+    for n in (1, 5, 37):  # 37: a ragged GEMM tail in M for every layer
+        say(f"[case] forward layers, batch {n}")
+        x, _ = inputs(n, 100 + n)
+        z = net.forward(to_dev(torch, x)).cpu().numpy()
+        a = x
+        for l in range(4):
+            act = ocnn.bf16(np.maximum(ocnn.conv3x3(a, P[f"conv{l + 1}.w"], P[f"conv{l + 1}.b"]), 0.0))
+            ref, _ = ocnn.maxpool2(act)
+            got = net.activation(l, n).transpose(0, 3, 1, 2)  # NHWC -> NCHW
+            close_bf16(got, ref, f"conv{l + 1} pooled")
+            a = got  # next layer from the GPU's own input
+        flat = a.transpose(0, 2, 3, 1).reshape(n, -1)
+        href = ocnn.bf16(np.maximum(flat @ P["fc1.w"].T + P["fc1.b"], 0.0))
+        h = net.activation(4, n)
+        close_bf16(h, href, "fc1")
+        zref = h @ P["fc2.w"] + P["fc2.b"][0]
+        mag = np.abs(h) @ np.abs(P["fc2.w"]) + abs(P["fc2.b"][0])
+        assert np.all(np.abs(z - zref) <= 1e-5 * mag + 1e-6), (z, zref)
+        assert np.array_equal(net.activation(5, n), z)
+        # end to end from the same input
+        # end to end from the same input: a stored value that rounds the other
+        # way moves the logits by a few bf16 steps of their scale
+        zo, _ = ocnn.forward(p, x, exact=False)
+        dz = np.abs(z - zo).max() / (np.abs(zo).max() + 1e-3)
+        say(f"  logits end to end: max diff / scale {dz:.2e}")
+        assert dz <= 0.05
+    net.close()
+
+
+def test_gradients_match_oracle(env):
+    gsp, ctx, torch = env
+    net = gsp.Cnn(ctx, seed=4)
+    p = net.params().astype(np.float64)
+    for n in (3, 16):
+        say(f"[case] gradients, batch {n}")
+        x, y = inputs(n, 200 + n)
+        g, loss = net.gradients(to_dev(torch, x), torch.from_numpy(y.astype(np.float32)).cuda())
+        go, lo = ocnn.gradients(p, x, y, exact=False)
+        assert loss == pytest.approx(lo, rel=1e-3)
+        o = 0
+        errs = {}
+        for name, shape in ocnn.layout():
+            k = int(np.prod(shape))
+            errs[name] = rel_l2(g[o:o + k].astype(np.float64), go[o:o + k])
+            say(f"  {name}: rel L2 {errs[name]:.2e}")
+            o += k
+        # and against the float64 network, to show the bf16 storage is what differs
+        ge, _ = ocnn.gradients(p, x, y, exact=True)
+        say(f"  whole vector: vs storage oracle {rel_l2(g.astype(np.float64), go):.2e}, "
+            f"vs float64 network {rel_l2(g.astype(np.float64), ge):.2e}")
+        for name, e in errs.items():
+            assert e <= 2e-3, name
+    net.close()
+
+
+def test_train_step_is_adam_on_the_gradients(env):
+    gsp, ctx, torch = env
+    net = gsp.Cnn(ctx, seed=5)
+    x, y = inputs(8, 300)
+    xd, yd = to_dev(torch, x), torch.from_numpy(y.astype(np.float32)).cuda()
+    lr = 1e-3
+    p = net.params().astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in (1, 2, 3):
+        g, _ = net.gradients(xd, yd)
+        g = g.astype(np.float64)
+        net.train_step(xd, yd, lr)
+        got = net.params().astype(np.float64)
+        p, m, v = ocnn.adam(p, g, m, v, t, lr)
+        # train_step recomputes the gradient (atomic split-K sums: last-bit
+        # differences), so elements whose gradient nearly cancels are excluded
+        sig = np.abs(g) > 1e-4 * np.abs(g).max()
+        err = np.abs(got - p)
+        ok = err <= 2e-3 * lr + 2.0 ** -22 * np.abs(p)
+        say(f"  step {t}: significant {sig.mean():.3f}, matching {ok[sig].mean():.5f}, max err {err[sig].max():.2e}")
+        assert ok[sig].mean() >= 0.999
+        p = got  # continue from the GPU's parameters
+    net.close()
+
+
+def test_training_learns_a_separable_task(env):
+    gsp, ctx, torch = env
+    net = gsp.Cnn(ctx, seed=6)
+    rng = np.random.default_rng(400)
+
+    def batch(n):
+        y = (rng.random(n) < 0.5).astype(np.float32)
+        x = rng.normal(size=(n, 2, 64, 64))
+        x[y == 1, 0, 28:36, 56:64] += 2.0  # a bright patch in the DM-time image
+        return to_dev(torch, x), torch.from_numpy(y).cuda()
+
+    losses = []
+    for it in range(60):
+        xd, yd = batch(64)
+        losses.append(net.train_step(xd, yd, 1e-3))
+    xd, yd = batch(256)
+    z = net.forward(xd).cpu().numpy()
+    acc = np.mean((z > 0) == (yd.cpu().numpy() > 0.5))
+    say(f"  loss {losses[0]:.3f} -> {np.mean(losses[-5:]):.3f}, held-out accuracy {acc:.3f}")
+    assert np.mean(losses[-5:]) < 0.5 * losses[0]
+    assert acc >= 0.95
+    net.close()
+
+
+def test_save_load_roundtrip(env, tmp_path):
+    gsp, ctx, torch = env
+    a = gsp.Cnn(ctx, seed=7)
+    b = gsp.Cnn(ctx, seed=8)
+    assert not np.array_equal(a.params(), b.params())
+    a.save(str(tmp_path / "w.bin"))
+    b.load(str(tmp_path / "w.bin"))
+    assert np.array_equal(a.params(), b.params())
+    x, _ = inputs(4, 500)
+    xd = to_dev(torch, x)
+    assert torch.equal(a.forward(xd), b.forward(xd))
+    a.close()
+    b.close()
+
+
+# --- cutouts -------------------------------------------------------------------
+
+def cutout_case(env, w, extra):
+    """GPU cutouts of the search's candidates plus `extra` (seg, dm_index,
+    t_peak, width) against the oracle, bf16 bit for bit up to rare one-step
+    rounding differences."""
+    gsp, ctx, torch = env
+    X = w.generate()
+    fb = torch.from_numpy(X).cuda()
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold)
+    c = c[np.argsort(-c["snr"])][:12]
+    more = np.zeros(len(extra), c.dtype)
+    for k, (s, i, t, wd) in enumerate(extra):
+        more[k]["seg"], more[k]["dm_index"], more[k]["t_peak"], more[k]["width"] = s, i, t, wd
+    c = np.concatenate([c, more])
+    say(f"[case] cutouts {w.name}: {len(c)} candidates, widths {sorted(set(c['width'].tolist()))}")
+    out = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, c).cpu().numpy().view(np.uint16)
+    rows = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    per_row = {}
+    total_px, diff_px = 0, 0
+    for k, cand in enumerate(c):
+        s = int(cand["seg"])
+        if s not in per_row:
+            seg = w.segments[s]
+            per_row[s] = (rows[s], np.array([oracle.stats(r)[0] for r in rows[s]]), oracle.downsample(X, seg[3]),
+                          oracle.delay_table(w.freqs, w.tsamp, seg))
+        row, mu, Y, delays = per_row[s]
+        ref = ocnn.bf16_bits(ocnn.cutout(row, mu, Y, delays, (cand["dm_index"], cand["t_peak"], cand["width"])))
+        got = out[k]
+        g = ocnn.from_bf16_bits(got)
+        r = ocnn.from_bf16_bits(ref)
+        assert np.all(np.abs(g - r) <= 2.0 ** -7 * np.maximum(np.abs(g), np.abs(r)) + 1e-6), k
+        total_px += got.size
+        diff_px += int(np.sum(got != ref))
+    say(f"  pixels differing by one rounding step: {diff_px} of {total_px}")
+    assert diff_px <= 1e-3 * total_px
+
+
+def test_cutouts_tiny(env):
+    w = synth.tiny()
+    # near the start (bins before the data), near the end, edge trials, widths up to r = 8
+    cutout_case(env, w, [(0, 0, 0, 1), (0, 5, 3, 40), (0, 199, 14072 - 64, 64), (0, 100, 500, 17),
+                         (0, 57, 7000, 200)])
+
+
+def test_cutouts_multirow(env):
+    segs = [(0.0, 1.0, 40, 1), (40.0, 2.0, 70, 2), (180.0, 4.0, 12, 4)]
+    w = synth.small(nchan=192, nsamp=6000, segments=segs, n_pulses=3, seed_offset=60, widths=[1, 2, 4, 8, 16, 32])
+    desc_rows = [(1, 69, 10, 16), (2, 11, 0, 3), (2, 0, 200, 33), (1, 30, 1, 2)]
+    cutout_case(env, w, desc_rows)
+
+
+def test_cutouts_invalid_candidates_give_zero_images(env):
+    gsp, ctx, torch = env
+    w = synth.tiny()
+    X = w.generate()
+    fb = torch.from_numpy(X).cuda()
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    bad = np.zeros(4, gsp.CAND_DTYPE)
+    bad["seg"] = [1, 0, 0, -1]
+    bad["dm_index"] = [0, 200, 3, 0]
+    bad["t_peak"] = [10, 10, 14072, 10]
+    bad["width"] = [4, 4, 1, 4]
+    out = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, bad).cpu().numpy()
+    assert (out == 0).all()
