@@ -157,6 +157,7 @@ def main():
     ap.add_argument("--workload", default="realistic", choices=["realistic", "wideband", "tiny"])
     ap.add_argument("--cpu-every", type=int, default=96, help="oracle sample: every n-th trial per row")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cnn", action="store_true", help="plain search only (no cutouts + network triage)")
     ap.add_argument("--stream", choices=["paced", "unpaced"], default=None,
                     help="run the 19-beam streaming workload instead (prints its own JSON line)")
     ap.add_argument("--stream-max-blocks", type=int, default=None)
@@ -190,10 +191,23 @@ def main():
     dmt = torch.empty(desc.total, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
 
+    net = None if args.no_cnn else gsp.Cnn(ctx, seed=1)
+    cut = torch.empty((4096, 2, 64, 64), dtype=torch.int16, device="cuda:0")
+    logits = torch.empty(4096, dtype=torch.float32, device="cuda:0")
+    t_triage = [0.0]
+
     def step():
         ctx.dedisperse(fb, w.freqs, desc, out=dmt, stream=stream)
         c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold, stream=stream)
         rep, ng = gsp.group_candidates(c)
+        if net is not None and ng:
+            # triage: cutouts of each event's representative, network scores
+            t = time.perf_counter()
+            ev = c[rep][:cut.shape[0]]
+            x = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, ev, out=cut[:len(ev)], stream=stream)
+            net.forward(x, out=logits[:len(ev)], stream=stream)
+            keep = int((logits[:len(ev)] > 0).sum().item())
+            t_triage[0] += time.perf_counter() - t
         return c, ng
 
     for k in range(args.warmup):
@@ -204,6 +218,7 @@ def main():
     ctx.profile_enable(True)
     ctx.profile_read(reset=True)
     torch.cuda.synchronize()
+    t_triage[0] = 0.0
     t = time.perf_counter()
     for _ in range(args.steps):
         c, ng = step()
@@ -231,6 +246,11 @@ def main():
                      "kernel": "k_dedisp", "work": "integer adds (n_dm * n_out * nchan per launch)"},
         "kernels": kernels,
         "candidates": int(len(c)), "events": int(ng),
+        "triage": None if net is None else {
+            "ms_per_step": t_triage[0] / args.steps * 1e3,
+            "what": "cutouts of each event's max-SNR candidate + CNN forward (490,897 parameters, random "
+                    "initialisation: timing only) + logits to host",
+            "plain_ms_per_step": ms - t_triage[0] / args.steps * 1e3},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

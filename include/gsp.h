@@ -203,7 +203,9 @@ int gsp_stream_open_beam(gsp_stream *s, int32_t nchan, const double *freqs_mhz, 
 /* block_host: uint8 [nsamp][nchan] time-major, copied before return;
  * nsamp < block_nsamp marks the beam's last block. */
 int gsp_stream_push(gsp_stream *s, int32_t beam_id, const uint8_t *block_host, int64_t nsamp);
-/* No more blocks; the beam's memory is released after its last block. */
+/* No more blocks; the beam's memory is released after its last block.
+ * A beam whose last block (short block, or the last one before close) has
+ * been processed is removed: its id is then unknown (GSP_EINVAL). */
 int gsp_stream_close_beam(gsp_stream *s, int32_t beam_id);
 /* Caller-driven processing: one step (*n_blocks = blocks processed, 0 if idle). */
 int gsp_stream_step(gsp_stream *s, int64_t *n_blocks);

@@ -84,7 +84,9 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       const int u = min(tid + i * nthreads, nu - 1);  // clamped: loads stay in bounds
       const int cl = u / U;
       const int p = u - cl * U;
-      const int64_t e0 = t0 + bj[cl] + 16 * (int64_t)p;  // multiple of 4
+      int64_t e0 = t0 + bj[cl] + 16 * (int64_t)p;  // multiple of 4
+      if (a.ring)  // ring position; the 17 samples read may run into the mirrored guard
+        e0 = (uint32_t)(t_rel + bj[cl] + 16 * p + a.phys0) % (uint32_t)a.ring;
       rows[i] = Y + (int64_t)(cs + cl) * a.pitch + e0;
     }
 #pragma unroll
