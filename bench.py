@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--stream", choices=["paced", "unpaced"], default=None,
                     help="run the 19-beam streaming workload instead (prints its own JSON line)")
     ap.add_argument("--stream-max-blocks", type=int, default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU only: this build has no multi-GPU path (beams or DM ranges would shard "
@@ -179,6 +181,14 @@ def main():
                           "4096 ch over 1000-1500 MHz, tsamp 49.152 us, 20480-sample blocks, lengths 2^18..2^20, "
                           "1000-4000 trials per beam"}, "stream": r}), flush=True)
         return
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1, out=dst)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
 
     w = workload(args.workload)
     log(f"generating {w.name}: {w.nsamp} x {w.nchan}")

@@ -283,3 +283,30 @@ def stream_beams(n_beams: int = 19, seed_offset: int = 0) -> list:
         w.pulses = _random_pulses(rng, 4, 0.05 * span, max(0.05 * span + 1.0, span - 9.0), 10.0, 1500.0)
         beams.append(_with_amps(w))
     return beams
+
+
+def triage_beam(k: int, split: str = "train", nsamp: int = 1 << 17, n_pulses: int = 8, n_spikes: int = 6,
+                burst_frac: float = 0.05) -> Workload:
+    """Beams for training and testing the triage network: the realistic band
+    and sampling, 2^17 samples (6.44 s), the ladder truncated at DM 1500
+    (3350 trials), `n_pulses` pulses (DM log-uniform 10-1500, FWHM
+    log-uniform 0.5-20 ms, SNR uniform 6-30) and RFI of the wideband kind:
+    sinusoid bursts in 5 % of the channels and zero-DM broadband spikes of
+    +40 over 1-3 samples.  `split` ("train", "val", "test") selects disjoint
+    beam numbers, hence independent noise, pulses and RFI."""
+    beam = {"train": 1000, "val": 300000, "test": 600000}[split] + k
+    w = Workload(f"triage-{split}{k}", 4096, 1000.0, 1500.0, 49.152e-6, nsamp, ladder(1500.0), WIDTHS_512, 6.0,
+                 BASE_SEED + 5, beam=beam)
+    rng = np.random.default_rng([BASE_SEED + 5, beam])
+    span = nsamp * w.tsamp
+    # the D=8 row's largest delay (DM 1500) is about 3.45 s
+    w.pulses = _random_pulses(rng, n_pulses, 0.15, span - 3.6, 10.0, 1500.0)
+    chans = rng.choice(w.nchan, size=int(round(burst_frac * w.nchan)), replace=False)
+    for c in chans:
+        dur = float(rng.uniform(0.1, 2.0))
+        t0 = float(rng.uniform(0.0, span - dur))
+        w.bursts.append((int(c), t0, dur, float(rng.uniform(20, 60)), float(rng.uniform(2, 50)),
+                         float(rng.uniform(0, 2 * math.pi))))
+    for _ in range(n_spikes):
+        w.spikes.append((int(rng.integers(0, nsamp - 4)), int(rng.integers(1, 4)), 40.0))
+    return _with_amps(w)

@@ -1,0 +1,224 @@
+"""Learned triage of single-pulse candidates: training data, training and
+evaluation of the library's network.
+
+The paper lists classification of candidates as the stage between the search
+and the candidate database (Section 2.1, Section 4) without fixing a
+classifier.  Here candidates of the GPU pipeline on seeded synthetic beams
+(synth.triage_beam: injected pulses, narrowband bursts, zero-DM spikes) are
+labelled by their injections, cut out (gsp_cutouts) and used to train the
+CNN (gsp_cnn_train_step).  Evaluation compares, on held-out beams, the events
+(friends-of-friends groups) passed on by the plain search with those whose
+representative the network accepts:
+    recall  = injected pulses with at least one matching passed event / pulses,
+    events  = number of events passed on.
+
+Run: python -m paper_2110_12749_amd.triage --train-beams 60 --test-beams 30
+(one JSON line on stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import gsp, synth
+
+K_DISP = 4148.808  # s MHz^2 cm^3 / pc
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def match_pulses(cands: np.ndarray, w: synth.Workload) -> np.ndarray:
+    """Index of the injected pulse each candidate belongs to, -1 for none.
+
+    A candidate at trial DM' matches a pulse (DM, t0, FWHM) when
+    |DM' - DM| <= DM/2 + 5 and its box centre time lies within the pulse's
+    arrival window at that trial: dedispersing at the wrong DM leaves the
+    channels' residual delays K |DM' - DM| (f^-2 - f_max^-2) spread over
+    [0, K |DM' - DM| (f_min^-2 - f_max^-2)], on the early side for DM' > DM
+    and the late side otherwise; the window adds 3 FWHM and the box width."""
+    out = np.full(len(cands), -1, np.int64)
+    if not len(cands) or not w.pulses:
+        return out
+    f = w.freqs
+    span = K_DISP * (1.0 / f.min() ** 2 - 1.0 / f.max() ** 2)
+    dms = cands["dm"]
+    t = cands["time_s"]
+    box = cands["width"] * np.array([w.segments[s][3] for s in cands["seg"]]) * w.tsamp
+    best = np.full(len(cands), np.inf)
+    for k, p in enumerate(w.pulses):
+        dd = dms - p.dm
+        lo = p.t0_s - np.where(dd > 0, span * dd, 0.0) - 3 * p.fwhm_s - box
+        hi = p.t0_s + np.where(dd < 0, -span * dd, 0.0) + 3 * p.fwhm_s + box
+        ok = (np.abs(dd) <= 0.5 * p.dm + 5.0) & (t >= lo) & (t <= hi)
+        dist = np.abs(dd)
+        take = ok & (dist < best)
+        out[take] = k
+        best[take] = dist[take]
+    return out
+
+
+class Beam:
+    """One beam through the GPU pipeline: dedispersion, search, grouping."""
+
+    def __init__(self, ctx: gsp.Context, w: synth.Workload, torch):
+        self.w = w
+        X = w.generate()
+        self.fb = torch.from_numpy(X).to("cuda:0")
+        del X
+        self.desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+        self.dmt = ctx.dedisperse(self.fb, w.freqs, self.desc)
+        self.cands = ctx.single_pulse_search(self.dmt, self.desc, w.widths, w.threshold)
+        self.rep, self.n_events = gsp.group_candidates(self.cands)
+        self.pulse = match_pulses(self.cands, w)
+
+    def events(self) -> np.ndarray:
+        """Candidate index of each event's representative."""
+        return np.unique(self.rep)
+
+    def release(self):
+        self.fb = self.dmt = None
+
+
+def pick_candidates(b: Beam, per_event: int, rng) -> np.ndarray:
+    """Up to `per_event` candidates of every event, the representative always
+    included."""
+    pick = []
+    for e in b.events():
+        members = np.flatnonzero(b.rep == b.rep[e])
+        others = members[members != e]
+        extra = rng.choice(others, size=min(len(others), per_event - 1), replace=False) if len(others) else []
+        pick.extend([e, *extra])
+    return np.asarray(pick, np.int64)
+
+
+def balance(torch, xs, ys, rng) -> tuple:
+    """Concatenate and balance 1:1 by subsampling the larger class."""
+    x = torch.cat(xs)
+    y = np.concatenate(ys)
+    pos, neg = np.flatnonzero(y == 1), np.flatnonzero(y == 0)
+    n = min(len(pos), len(neg))
+    keep = np.concatenate([rng.choice(pos, n, replace=False), rng.choice(neg, n, replace=False)])
+    rng.shuffle(keep)
+    kd = torch.from_numpy(keep).to(x.device)
+    return x.index_select(0, kd).contiguous(), torch.from_numpy(y[keep]).to(x.device), int(len(pos)), int(len(neg))
+
+
+def train(net: gsp.Cnn, x, y, steps: int, batch: int, lr: float, rng, torch) -> list:
+    n = x.shape[0]
+    losses = []
+    for it in range(steps):
+        idx = torch.from_numpy(rng.integers(0, n, batch)).to(x.device)
+        rate = lr * (0.1 if it >= int(0.8 * steps) else 1.0)
+        loss = net.train_step(x.index_select(0, idx).contiguous(), y.index_select(0, idx).contiguous(), rate,
+                              want_loss=(it % 50 == 0 or it == steps - 1))
+        if loss is not None:
+            losses.append((it, loss))
+            log(f"  step {it}: loss {loss:.4f}")
+    return losses
+
+
+def event_scores(ctx, net, torch, b: Beam) -> tuple:
+    """(representative indices, logits) of a beam's events."""
+    ev = b.events()
+    if not len(ev):
+        return ev, np.zeros(0, np.float32)
+    x = gsp.cutouts(ctx, b.fb, b.w.freqs, b.dmt, b.desc, b.cands[ev])
+    return ev, net.forward(x).cpu().numpy()
+
+
+def recall_and_events(beams_scores, tau: float | None) -> tuple:
+    """(recall, events passed, pulses) over beams, for logit threshold tau
+    (None: the plain search, every event passes)."""
+    found, total, passed = 0, 0, 0
+    for b, ev, z in beams_scores:
+        keep = ev if tau is None else ev[z > tau]
+        passed += len(keep)
+        hit = set(int(k) for k in b.pulse[keep] if k >= 0)
+        found += len(hit)
+        total += len(b.w.pulses)
+    return found / max(1, total), passed, total
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-beams", type=int, default=60)
+    ap.add_argument("--val-beams", type=int, default=10)
+    ap.add_argument("--test-beams", type=int, default=30)
+    ap.add_argument("--per-event", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--save", default=None, help="write the trained parameters here")
+    args = ap.parse_args()
+    import torch
+    rng = np.random.default_rng(args.seed)
+    ctx = gsp.Context(0)
+    t0 = time.perf_counter()
+
+    xs, ys = [], []
+    for k in range(args.train_beams):
+        b = Beam(ctx, synth.triage_beam(k, "train"), torch)
+        pick = pick_candidates(b, args.per_event, rng)
+        if len(pick):
+            xs.append(gsp.cutouts(ctx, b.fb, b.w.freqs, b.dmt, b.desc, b.cands[pick]))
+            ys.append((b.pulse[pick] >= 0).astype(np.float32))
+        log(f"train beam {k}: {len(b.cands)} candidates, {b.n_events} events, "
+            f"{int((b.pulse >= 0).sum())} matched to pulses, {len(pick)} cutouts")
+        b.release()
+    x, y, npos, nneg = balance(torch, xs, ys, rng)
+    del xs
+    torch.cuda.empty_cache()
+    log(f"training set: {x.shape[0]} cutouts (balanced from {npos} positive, {nneg} negative)")
+    net = gsp.Cnn(ctx, seed=args.seed)
+    t_train = time.perf_counter()
+    losses = train(net, x, y, args.steps, args.batch, args.lr, rng, torch)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    if args.save:
+        net.save(args.save)
+    del x, y
+
+    def scored(split, n):
+        out = []
+        for k in range(n):
+            b = Beam(ctx, synth.triage_beam(k, split), torch)
+            ev, z = event_scores(ctx, net, torch, b)
+            out.append((b, ev, z))
+            log(f"{split} beam {k}: {len(b.cands)} candidates, {b.n_events} events, "
+                f"{int((z > 0).sum())} accepted")
+            b.release()
+        return out
+
+    val = scored("val", args.val_beams)
+    pos_logits = np.concatenate([z[b.pulse[ev] >= 0] for b, ev, z in val]) if val else np.zeros(0)
+    # threshold: keep 99.5 % of the validation events matched to pulses, never above 0
+    tau = min(0.0, float(np.quantile(pos_logits, 0.005))) if len(pos_logits) else 0.0
+    test = scored("test", args.test_beams)
+    r_plain, e_plain, n_pulses = recall_and_events(test, None)
+    r_cnn, e_cnn, _ = recall_and_events(test, tau)
+    r_cnn0, e_cnn0, _ = recall_and_events(test, 0.0)
+    print(json.dumps({
+        "train": {"beams": args.train_beams, "cutouts": int(2 * min(npos, nneg)), "positive": npos,
+                  "negative": nneg, "steps": args.steps, "batch": args.batch, "seconds": t_train,
+                  "loss_first": losses[0][1], "loss_last": losses[-1][1]},
+        "threshold": tau,
+        "test": {"beams": args.test_beams, "pulses": n_pulses,
+                 "plain": {"recall": r_plain, "events": e_plain},
+                 "cnn": {"recall": r_cnn, "events": e_cnn},
+                 "cnn_tau0": {"recall": r_cnn0, "events": e_cnn0},
+                 "recall_ratio": r_cnn / r_plain if r_plain else None,
+                 "events_ratio": e_cnn / e_plain if e_plain else None},
+        "wall_s": time.perf_counter() - t0}), flush=True)
+    net.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
