@@ -51,6 +51,39 @@ def describe(w, desc):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_realistic_traffic.md")
+DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", f) for f in ("dedisp_tile.h", "dedisp.hip")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEDISP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name: str):
+    """HBM bytes per dedispersion launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel), or None
+    when there is none for this workload or the kernel source changed since."""
+    if workload_name != "realistic" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", "|", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, X, desc, every: int):
     """The oracle as it stands, on a deterministic sample of the trials
     (every `every`-th trial of each row, full time range, dedispersion and
@@ -252,7 +285,8 @@ def main():
         "vs_baseline": None, "dtype": "u8->int32", "data": "synthetic", "config": cfg,
         "rtf": rtf,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                     "frac": achieved / PEAK_INT32_OPS, "traffic": measured_traffic(w.name),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_dedisp", "work": "integer adds (n_dm * n_out * nchan per launch)"},
         "kernels": kernels,
         "candidates": int(len(c)), "events": int(ng),
