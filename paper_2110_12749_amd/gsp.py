@@ -10,6 +10,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: it ships its own HIP runtime (same soname as ROCm's), and the
+# library must bind to that one; loading the library first would bring a
+# second HIP/HSA runtime into the process.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsp.so")
