@@ -37,11 +37,13 @@ def match_pulses(cands: np.ndarray, w: synth.Workload) -> np.ndarray:
     """Index of the injected pulse each candidate belongs to, -1 for none.
 
     A candidate at trial DM' matches a pulse (DM, t0, FWHM) when
-    |DM' - DM| <= DM/2 + 5 and its box centre time lies within the pulse's
-    arrival window at that trial: dedispersing at the wrong DM leaves the
+    |DM' - DM| <= max(2, 0.05 DM), its box centre time lies within the
+    pulse's arrival window at that trial, and its box is no longer than the
+    pulse as seen at that trial.  Dedispersing at the wrong DM leaves the
     channels' residual delays K |DM' - DM| (f^-2 - f_max^-2) spread over
-    [0, K |DM' - DM| (f_min^-2 - f_max^-2)], on the early side for DM' > DM
-    and the late side otherwise; the window adds 3 FWHM and the box width."""
+    S = K |DM' - DM| (f_min^-2 - f_max^-2), on the early side for DM' > DM
+    and the late side otherwise; the window adds 3 FWHM and the box width,
+    and the box may span up to 4 (FWHM + S) + 1 ms."""
     out = np.full(len(cands), -1, np.int64)
     if not len(cands) or not w.pulses:
         return out
@@ -55,7 +57,8 @@ def match_pulses(cands: np.ndarray, w: synth.Workload) -> np.ndarray:
         dd = dms - p.dm
         lo = p.t0_s - np.where(dd > 0, span * dd, 0.0) - 3 * p.fwhm_s - box
         hi = p.t0_s + np.where(dd < 0, -span * dd, 0.0) + 3 * p.fwhm_s + box
-        ok = (np.abs(dd) <= 0.5 * p.dm + 5.0) & (t >= lo) & (t <= hi)
+        ok = ((np.abs(dd) <= max(2.0, 0.05 * p.dm)) & (t >= lo) & (t <= hi)
+              & (box <= 4.0 * (p.fwhm_s + span * np.abs(dd)) + 1e-3))
         dist = np.abs(dd)
         take = ok & (dist < best)
         out[take] = k
@@ -85,16 +88,25 @@ class Beam:
         self.fb = self.dmt = None
 
 
-def pick_candidates(b: Beam, per_event: int, rng) -> np.ndarray:
-    """Up to `per_event` candidates of every event, the representative always
-    included."""
+def pick_candidates(b: Beam, per_event: int, per_pulse: int, rng) -> np.ndarray:
+    """Training candidates of a beam: every event's representative plus up
+    to per_event - 1 other members, with the candidates matched to any one
+    injected pulse capped at per_pulse (a bright pulse yields thousands of
+    near-identical candidates, a faint one a handful; the cap keeps the
+    faint ones from being outweighed)."""
     pick = []
     for e in b.events():
         members = np.flatnonzero(b.rep == b.rep[e])
         others = members[members != e]
         extra = rng.choice(others, size=min(len(others), per_event - 1), replace=False) if len(others) else []
         pick.extend([e, *extra])
-    return np.asarray(pick, np.int64)
+    pick = np.unique(np.asarray(pick, np.int64))
+    pos = b.pulse[pick]
+    keep = [pick[pos < 0]]
+    for k in np.unique(pos[pos >= 0]):
+        mine = pick[pos == k]
+        keep.append(rng.choice(mine, size=min(len(mine), per_pulse), replace=False))
+    return np.sort(np.concatenate(keep))
 
 
 def balance(torch, xs, ys, rng) -> tuple:
@@ -116,7 +128,7 @@ def train(net: gsp.Cnn, x, y, steps: int, batch: int, lr: float, rng, torch) -> 
         idx = torch.from_numpy(rng.integers(0, n, batch)).to(x.device)
         rate = lr * (0.1 if it >= int(0.8 * steps) else 1.0)
         loss = net.train_step(x.index_select(0, idx).contiguous(), y.index_select(0, idx).contiguous(), rate,
-                              want_loss=(it % 50 == 0 or it == steps - 1))
+                              want_loss=(it % 250 == 0 or it == steps - 1))
         if loss is not None:
             losses.append((it, loss))
             log(f"  step {it}: loss {loss:.4f}")
@@ -148,13 +160,15 @@ def recall_and_events(beams_scores, tau: float | None) -> tuple:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-beams", type=int, default=60)
-    ap.add_argument("--val-beams", type=int, default=10)
+    ap.add_argument("--val-beams", type=int, default=16)
     ap.add_argument("--test-beams", type=int, default=30)
     ap.add_argument("--per-event", type=int, default=16)
-    ap.add_argument("--steps", type=int, default=1500)
-    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--per-pulse", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--margin", type=float, default=0.5, help="logit margin below the weakest validation pulse")
     ap.add_argument("--save", default=None, help="write the trained parameters here")
     args = ap.parse_args()
     import torch
@@ -165,7 +179,7 @@ def main():
     xs, ys = [], []
     for k in range(args.train_beams):
         b = Beam(ctx, synth.triage_beam(k, "train"), torch)
-        pick = pick_candidates(b, args.per_event, rng)
+        pick = pick_candidates(b, args.per_event, args.per_pulse, rng)
         if len(pick):
             xs.append(gsp.cutouts(ctx, b.fb, b.w.freqs, b.dmt, b.desc, b.cands[pick]))
             ys.append((b.pulse[pick] >= 0).astype(np.float32))
@@ -197,13 +211,31 @@ def main():
         return out
 
     val = scored("val", args.val_beams)
-    pos_logits = np.concatenate([z[b.pulse[ev] >= 0] for b, ev, z in val]) if val else np.zeros(0)
-    # threshold: keep 99.5 % of the validation events matched to pulses, never above 0
-    tau = min(0.0, float(np.quantile(pos_logits, 0.005))) if len(pos_logits) else 0.0
+    # threshold: below the best logit of every validation pulse the plain
+    # search finds (each such pulse keeps at least one event), by a margin
+    best = []
+    for b, ev, z in val:
+        k = b.pulse[ev]
+        for pk in np.unique(k[k >= 0]):
+            best.append(float(z[k == pk].max()))
+    tau = min(best) - args.margin if best else 0.0
     test = scored("test", args.test_beams)
     r_plain, e_plain, n_pulses = recall_and_events(test, None)
     r_cnn, e_cnn, _ = recall_and_events(test, tau)
     r_cnn0, e_cnn0, _ = recall_and_events(test, 0.0)
+    # pulses the plain search finds but the network rejects at tau
+    lost = []
+    for b, ev, z in test:
+        k = b.pulse[ev]
+        for pk in np.unique(k[k >= 0]):
+            zb = float(z[k == pk].max())
+            if zb <= tau:
+                p = b.w.pulses[int(pk)]
+                i = ev[k == pk][np.argmax(z[k == pk])]
+                lost.append({"dm": round(p.dm, 2), "fwhm_ms": round(p.fwhm_s * 1e3, 2), "snr": round(p.snr, 2),
+                             "t0_s": round(p.t0_s, 3), "best_logit": round(zb, 3),
+                             "event_snr": round(float(b.cands["snr"][i]), 2), "event_width": int(b.cands["width"][i]),
+                             "event_dm": round(float(b.cands["dm"][i]), 2)})
     print(json.dumps({
         "train": {"beams": args.train_beams, "cutouts": int(2 * min(npos, nneg)), "positive": npos,
                   "negative": nneg, "steps": args.steps, "batch": args.batch, "seconds": t_train,
@@ -214,7 +246,7 @@ def main():
                  "cnn": {"recall": r_cnn, "events": e_cnn},
                  "cnn_tau0": {"recall": r_cnn0, "events": e_cnn0},
                  "recall_ratio": r_cnn / r_plain if r_plain else None,
-                 "events_ratio": e_cnn / e_plain if e_plain else None},
+                 "events_ratio": e_cnn / e_plain if e_plain else None, "lost": lost},
         "wall_s": time.perf_counter() - t0}), flush=True)
     net.close()
     ctx.close()

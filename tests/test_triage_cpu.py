@@ -21,11 +21,13 @@ def test_match_pulses_windows():
         (1, 310.0, 1.0 + 0.05, 8),              # higher DM but late: outside
         (1, 290.0, 1.0 + 0.5 * span * 10, 8),   # lower DM: arrives late, inside
         (0, 20.5, 2.0, 2),                      # second pulse
-        (0, 4.0, 2.0, 2),                       # DM too far from 20 (|dd| > 20/2 + 5)
+        (0, 17.5, 2.0, 2),                      # DM too far from 20 (|dd| > max(2, 0.05 * 20))
         (0, 20.0, 3.0, 2),                      # no pulse at that time
+        (0, 20.0, 2.0, 512),                    # box far longer than the pulse
+        (1, 320.0, 1.0, 8),                     # DM too far from 300 (|dd| > 15)
     ])
     got = triage.match_pulses(c, w)
-    assert got.tolist() == [0, 0, -1, 0, 1, -1, -1]
+    assert got.tolist() == [0, 0, -1, 0, 1, -1, -1, -1, -1]
 
 
 def test_triage_beams_are_disjoint_and_seeded():
