@@ -53,6 +53,7 @@ enum {
 #define GSP_MAX_SEG 16
 
 typedef struct gsp_ctx gsp_ctx;
+typedef struct gsp_cnn gsp_cnn; /* triage network, declared with its functions below */
 
 /* One context per host thread on `device`.  Owns delay tables, staging and
  * search scratch, and the tuned launch shapes. */
@@ -181,6 +182,8 @@ typedef struct gsp_stream_candidate {
   int32_t beam;   /* beam id */
   int32_t block;  /* index of the beam's block whose window held the run */
   gsp_candidate c; /* times in absolute samples of the row since the beam's start */
+  float score;    /* triage network logit (NaN when no network is attached) */
+  int32_t reserved;
 } gsp_stream_candidate;
 
 typedef struct gsp_stream_stats {
@@ -190,6 +193,8 @@ typedef struct gsp_stream_stats {
   int64_t mem_used, mem_budget;           /* device bytes held by admitted beams */
   int32_t beams_active, beams_queued;
   int64_t blocks_pending;
+  int64_t triage_scored, triage_rejected; /* candidates scored / dropped by the network */
+  double triage_s;                        /* wall time of cutouts + network inside steps */
 } gsp_stream_stats;
 
 /* widths/threshold: the search of every beam (as gsp_single_pulse_search). */
@@ -207,6 +212,18 @@ int gsp_stream_push(gsp_stream *s, int32_t beam_id, const uint8_t *block_host, i
  * A beam whose last block (short block, or the last one before close) has
  * been processed is removed: its id is then unknown (GSP_EINVAL). */
 int gsp_stream_close_beam(gsp_stream *s, int32_t beam_id);
+/* Learned triage of streamed candidates (Sections 2.1 and 4 name the
+ * classification stage; see gsp_cutouts and gsp_cnn_*): with a network
+ * attached, each step cuts out its candidates from the stream's device state
+ * (the window of dedispersed series with the look-back before it, the ring
+ * of downsampled samples; times before the beam's start count as the
+ * window's mean of the trial in the DM-time image and are left out of the
+ * frequency-time image, as in gsp_cutouts), scores them, and passes on only
+ * those with logit > threshold; gsp_stream_candidate.score carries the
+ * logit.  cnn = NULL detaches (the plain search: every candidate passes).
+ * The network must outlive its attachment; the worker thread must be
+ * stopped. */
+int gsp_stream_set_triage(gsp_stream *s, gsp_cnn *cnn, float threshold);
 /* Caller-driven processing: one step (*n_blocks = blocks processed, 0 if idle). */
 int gsp_stream_step(gsp_stream *s, int64_t *n_blocks);
 /* Library-driven processing: a worker thread steps whenever blocks are pending. */
@@ -320,7 +337,6 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, co
  *           b[cout];  fc1: w[192][2048], b[192];  fc2: w[192], b[1].
  * Loss: mean over the batch of the binary cross-entropy with logits;
  * optimiser Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected). */
-typedef struct gsp_cnn gsp_cnn;
 int64_t gsp_cnn_num_params(void);
 /* He-uniform weights drawn from `seed` (SplitMix64), zero biases. */
 int gsp_cnn_create(gsp_ctx *ctx, uint64_t seed, gsp_cnn **out);

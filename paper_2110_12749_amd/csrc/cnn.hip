@@ -312,10 +312,106 @@ struct CutoutArgs {
 //    samples; a bin partly before the start is scaled up to r samples, one
 //    wholly before it takes its band's mean.
 // Each image is then z-scored (zero mean, unit variance; constant -> 0).
+// The two images of one candidate from a data source:
+//   dm(tr, t)  the dedispersed sample of trial tr at time t >= 0;
+//   mean(tr)   the value counted for times before the start;
+//   ft(c, t)   channel c's downsampled sample t >= 0 shifted by its delay at
+//              the candidate's trial (t + d_c);
+// img: LDS [2][4096] doubles, red: LDS [3][256]; out: bf16 [2][4096].
+template <class DM, class MEAN, class FT>
+__device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int nchan, int rmax, DM dm, MEAN mean,
+                              FT ft, double (*img)[4096], double (*red)[256], uint16_t *out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = max(1, min(rmax, width / 8));
+  const int lo = max(0, min(dm_index - 32, n_dm - 64));
+  // ---- DM-time ----
+  for (int u = tid; u < 64 * 64; u += 256) {
+    const int q = u / 64, b = u % 64;
+    const int tr = lo + q;
+    double v = 0.0;
+    if (tr < n_dm) {
+      const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
+      for (int j = 0; j < r; ++j) {
+        const int64_t t = t0 + j;
+        v += t >= 0 ? (double)dm(tr, t) : mean(tr);
+      }
+    }
+    img[0][u] = v;
+  }
+  // ---- frequency-time: one wave per band, lanes over the band's channels ----
+  for (int band = wave; band < 64; band += 4) {
+    const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
+    double valid_sum = 0.0;
+    int n_valid_bins = 0;
+    for (int b = 0; b < 64; ++b) {
+      const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
+      double acc = 0.0;
+      for (int ch = cb + lane; ch < ce; ch += 64)
+        for (int j = 0; j < r; ++j)
+          if (t0 + j >= 0) acc += (double)ft(ch, t0 + j);
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      const int64_t first = max((int64_t)0, t0);
+      const int cnt = (int)max((int64_t)0, t0 + r - first);
+      const double v = cnt > 0 ? acc * (double)r / (double)cnt : NAN;
+      if (cnt > 0) {
+        valid_sum += v;
+        ++n_valid_bins;
+      }
+      if (lane == 0) img[1][band * 64 + b] = v;
+    }
+    if (lane == 0 && n_valid_bins < 64) {
+      const double fill = n_valid_bins ? valid_sum / n_valid_bins : 0.0;
+      for (int b = 0; b < 64; ++b)
+        if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
+    }
+  }
+  __syncthreads();
+  // ---- z-score each image (two passes; an image of equal pixels becomes 0) ----
+  for (int im = 0; im < 2; ++im) {
+    double s1 = 0.0, vmin = INFINITY, vmax = -INFINITY;
+    for (int u = tid; u < 4096; u += 256) {
+      const double v = img[im][u];
+      s1 += v;
+      vmin = fmin(vmin, v);
+      vmax = fmax(vmax, v);
+    }
+    red[0][tid] = s1;
+    red[1][tid] = vmin;
+    red[2][tid] = vmax;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) {
+        red[0][tid] += red[0][tid + h];
+        red[1][tid] = fmin(red[1][tid], red[1][tid + h]);
+        red[2][tid] = fmax(red[2][tid], red[2][tid + h]);
+      }
+      __syncthreads();
+    }
+    const double mean_px = red[0][0] / 4096.0;
+    const bool flat = red[1][0] == red[2][0];
+    __syncthreads();
+    double s2 = 0.0;
+    for (int u = tid; u < 4096; u += 256) {
+      const double d = img[im][u] - mean_px;
+      s2 += d * d;
+    }
+    red[0][tid] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) red[0][tid] += red[0][tid + h];
+      __syncthreads();
+    }
+    const double inv = flat ? 0.0 : 1.0 / sqrt(red[0][0] / 4096.0);
+    uint16_t *o = out + im * 4096;
+    for (int u = tid; u < 4096; u += 256) o[u] = d2bf((img[im][u] - mean_px) * inv);
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
   __shared__ double img[2][64 * 64];
   __shared__ double red[3][256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   for (int64_t k = blockIdx.x; k < a.n; k += gridDim.x) {
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
@@ -326,104 +422,50 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
       continue;
     }
     const CutRow R = a.row[c.seg];
-    const int64_t e = c.t_peak + c.width - 1;
-    const int r = max(1, min(a.rmax, c.width / 8));
-    const int lo = max(0, min(c.dm_index - 32, R.n_dm - 64));
-    // ---- DM-time ----
-    for (int u = tid; u < 64 * 64; u += 256) {
-      const int q = u / 64, b = u % 64;
-      const int tr = lo + q;
-      double v = 0.0;
-      if (tr < R.n_dm) {
-        const int32_t *x = R.dmt + (int64_t)tr * R.n_out;
-        const double mu = a.musig[2 * (R.trial0 + tr)];
-        double sacc = 0.0;
-        const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
-        for (int j = 0; j < r; ++j) {
-          const int64_t t = t0 + j;
-          sacc += t >= 0 ? (double)x[t] : mu;
-        }
-        v = sacc;
-      }
-      img[0][u] = v;
-    }
-    // ---- frequency-time: one wave per band, lanes over the band's channels ----
-    const int dmi = c.dm_index;
-    for (int band = wave; band < 64; band += 4) {
-      const int cb = (int)((int64_t)band * a.nchan / 64), ce = (int)((int64_t)(band + 1) * a.nchan / 64);
-      double valid_sum = 0.0;
-      int n_valid_bins = 0;
-      for (int b = 0; b < 64; ++b) {
-        const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
-        double acc = 0.0;
-        int cnt = 0;
-        for (int ch = cb + lane; ch < ce; ch += 64) {
-          const int64_t d = R.delays[(int64_t)dmi * a.nchan + ch];
-          for (int j = 0; j < r; ++j) {
-            const int64_t t = t0 + j;
-            if (t < 0) continue;
-            const uint8_t *p = a.fb + ((t + d) * R.D) * (int64_t)a.nchan + ch;
-            for (int m = 0; m < R.D; ++m) acc += p[(int64_t)m * a.nchan];
-          }
-        }
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        const int64_t first = max((int64_t)0, t0);
-        cnt = (int)max((int64_t)0, t0 + r - first);
-        const double v = cnt > 0 ? acc * (double)r / (double)cnt : NAN;
-        if (cnt > 0) {
-          valid_sum += v;
-          ++n_valid_bins;
-        }
-        if (lane == 0) img[1][band * 64 + b] = v;
-      }
-      if (lane == 0 && n_valid_bins < 64) {
-        const double fill = n_valid_bins ? valid_sum / n_valid_bins : 0.0;
-        for (int b = 0; b < 64; ++b)
-          if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
-      }
-    }
-    __syncthreads();
-    // ---- z-score each image (two passes; an image of equal pixels becomes 0) ----
-    for (int im = 0; im < 2; ++im) {
-      double s1 = 0.0, vmin = INFINITY, vmax = -INFINITY;
-      for (int u = tid; u < 4096; u += 256) {
-        const double v = img[im][u];
-        s1 += v;
-        vmin = fmin(vmin, v);
-        vmax = fmax(vmax, v);
-      }
-      red[0][tid] = s1;
-      red[1][tid] = vmin;
-      red[2][tid] = vmax;
-      __syncthreads();
-      for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h) {
-          red[0][tid] += red[0][tid + h];
-          red[1][tid] = fmin(red[1][tid], red[1][tid + h]);
-          red[2][tid] = fmax(red[2][tid], red[2][tid + h]);
-        }
-        __syncthreads();
-      }
-      const double mean = red[0][0] / 4096.0;
-      const bool flat = red[1][0] == red[2][0];
-      __syncthreads();
-      double s2 = 0.0;
-      for (int u = tid; u < 4096; u += 256) {
-        const double d = img[im][u] - mean;
-        s2 += d * d;
-      }
-      red[0][tid] = s2;
-      __syncthreads();
-      for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h) red[0][tid] += red[0][tid + h];
-        __syncthreads();
-      }
-      const double inv = flat ? 0.0 : 1.0 / sqrt(red[0][0] / 4096.0);
-      uint16_t *o = a.out + ((int64_t)k * 2 + im) * 4096;
-      for (int u = tid; u < 4096; u += 256) o[u] = d2bf((img[im][u] - mean) * inv);
-      __syncthreads();
-    }
+    const uint8_t *fb = a.fb;
+    const int nchan = a.nchan;
+    const double *musig = a.musig;
+    const int32_t *dly = R.delays + (int64_t)c.dm_index * nchan;
+    auto dm = [&](int tr, int64_t t) { return R.dmt[(int64_t)tr * R.n_out + t]; };
+    auto mean = [&](int tr) { return musig[2 * (R.trial0 + tr)]; };
+    auto ft = [&](int ch, int64_t t) {
+      const uint8_t *p = fb + ((t + dly[ch]) * R.D) * (int64_t)nchan + ch;
+      uint32_t v = 0;
+      for (int m = 0; m < R.D; ++m) v += p[(int64_t)m * nchan];
+      return v;
+    };
+    cutout_images(c.t_peak + c.width - 1, c.width, c.dm_index, R.n_dm, nchan, a.rmax, dm, mean, ft, img, red,
+                  a.out + (int64_t)k * 2 * 4096);
   }
+}
+
+// Cutouts of streamed candidates from the stream's device state: the
+// dedispersed series of the current window (and the look-back kept before
+// it) and the ring of downsampled samples.  Times before the beam's start
+// count as the window's mean (DM-time) or are left out (frequency-time), as
+// for batch cutouts.
+__global__ __launch_bounds__(256) void k_cutout_stream(const StreamCut *__restrict__ cuts, int64_t n, int rmax,
+                                                       uint16_t *__restrict__ out) {
+  __shared__ double img[2][64 * 64];
+  __shared__ double red[3][256];
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const StreamCut C = cuts[k];
+    const int32_t *dly = C.delays + (int64_t)C.dm_index * C.nchan;
+    auto dm = [&](int tr, int64_t t) { return C.win[(int64_t)tr * C.win_pitch + C.look + (t - C.a)]; };
+    auto mean = [&](int tr) { return C.mu[2 * tr]; };
+    auto ft = [&](int ch, int64_t t) {
+      return (uint32_t)C.ring[(int64_t)ch * C.ring_pitch + (t + dly[ch]) % C.R];
+    };
+    cutout_images(C.t_peak + C.width - 1, C.width, C.dm_index, C.n_dm, C.nchan, rmax, dm, mean, ft, img, red,
+                  out + k * 2 * 4096);
+  }
+}
+
+void launch_cutouts_stream(const StreamCut *cuts_dev, int64_t n, uint16_t *out_dev, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cutout_stream, dim3((unsigned)std::min<int64_t>(n, 256 * 8)), dim3(256), 0, st, cuts_dev, n,
+                     8, out_dev);
+  check_hip(hipGetLastError(), "launch stream cutouts");
 }
 
 // ---------------------------------------------------------------------------

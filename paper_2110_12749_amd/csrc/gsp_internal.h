@@ -190,6 +190,20 @@ void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, 
                          hipStream_t st);
 
 void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
+// One streamed candidate's cutout sources (device state of its beam and row).
+struct StreamCut {
+  const int32_t *win;     // window buffer [n_dm][win_pitch]: column look + (t - a) holds time t
+  int64_t win_pitch;
+  int64_t a;              // absolute time of the window's first output
+  const double *mu;       // mu[2 * trial]: the window's mean of each trial of the row
+  const uint16_t *ring;   // downsampled samples [nchan][ring_pitch], time t at column t mod R
+  int64_t ring_pitch, R;
+  const int32_t *delays;  // [n_dm][nchan]
+  int64_t t_peak;
+  int32_t look, n_dm, nchan, dm_index, width;
+};
+void launch_cutouts_stream(const StreamCut *cuts_dev, int64_t n, uint16_t *out_dev, hipStream_t st);
+
 // Device pointer of per-trial mu/sigma (double[2*n_trials]) after launch_stats.
 const double *stats_musig(gsp_ctx *ctx, const gsp_dmt_desc *desc);
 void launch_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, const int32_t *widths_dev,

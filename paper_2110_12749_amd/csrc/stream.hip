@@ -36,6 +36,7 @@
 namespace gsp {
 
 static constexpr int kGuard = 32;          // mirrored samples past the ring end
+static constexpr int kCutoutReach = 512;   // samples a cutout reaches back from the box end
 static constexpr int kStreamGroups = 4;    // dedispersion shape used by streams
 static constexpr int kStreamTpw = 4;
 static constexpr int kStreamWaves = 8;
@@ -217,6 +218,7 @@ struct StreamRow {
   int64_t Wcap = 0;
   int64_t N = 0;          // downsampled samples received
   int64_t emitted = 0;    // end of the last window
+  int64_t last_w = 0;     // length of the window in the buffer (shifted out by the next step)
   // window of the last step (for read-back)
   int64_t last_a = 0, last_b = 0;
 };
@@ -272,6 +274,12 @@ struct gsp_stream {
   hipGraphExec_t exec = nullptr;
   int64_t graph_lds = -1;  // dedispersion LDS the graph was captured with
   bool use_graph = true;
+  // learned triage (optional): cutouts of each step's candidates scored by a network
+  gsp_cnn *cnn = nullptr;
+  float triage_thr = 0.f;
+  DevBuf d_cuts, d_cutimg, d_logits;
+  int64_t scored = 0, rejected = 0;
+  double triage_s = 0;
   // results
   std::vector<gsp_stream_candidate> out;
   std::vector<double> lat;
@@ -312,7 +320,7 @@ int64_t beam_bytes(const gsp_stream *s, const Beam &b) {
   for (const auto &r : b.rows) {
     m += (int64_t)b.nchan * (r->R + kGuard) * 2;
     m += (int64_t)r->n_dm * (s->look + r->Wcap) * 4;
-    m += (int64_t)r->tables.addr.bytes + (int64_t)r->tables.dmin.bytes;
+    m += (int64_t)r->tables.addr.bytes + (int64_t)r->tables.dmin.bytes + (int64_t)r->tables.delays_host.size() * 4;
   }
   return m;
 }
@@ -335,7 +343,9 @@ void plan_beam(gsp_stream *s, Beam &b) {
     row->n_dm = d.seg[r].n_dm;
     row->M = d.max_delay[r];
     row->Wcap = s->B / row->D;
-    row->R = (row->Wcap + row->M + 8 + 3) / 4 * 4;
+    // ring: the block, the maximum delay and kCutoutReach samples of history
+    // for the frequency-time cutouts of candidates
+    row->R = (row->Wcap + row->M + 8 + kCutoutReach + 3) / 4 * 4;
     row->tables.addr.device = s->ctx->device;
     row->tables.dmin.device = s->ctx->device;
     // the staged rows are uint16 for every D in a stream (one kernel instance)
@@ -352,6 +362,11 @@ void admit(gsp_stream *s, Beam &b) {
     r->ring.reserve((size_t)b.nchan * (r->R + kGuard) * 2);
     r->win.device = s->ctx->device;
     r->win.reserve((size_t)r->n_dm * (s->look + r->Wcap) * 4);
+    r->tables.delays_dev.device = s->ctx->device;
+    r->tables.delays_dev.reserve(r->tables.delays_host.size() * 4);
+    check_hip(hipMemcpy(r->tables.delays_dev.ptr, r->tables.delays_host.data(), r->tables.delays_host.size() * 4,
+                        hipMemcpyHostToDevice),
+              "copy delays");
   }
   b.admitted = true;
   s->used += b.mem;
@@ -390,6 +405,10 @@ void set_attributes(gsp_stream *s, int64_t dd_lds) {
 void launch_sequence(gsp_stream *s, int64_t dd_lds) {
   gsp_ctx *ctx = nullptr;
   hipStream_t st = s->st;
+  // the previous window's look-back shift first: after a step the window
+  // buffer still holds [look-back | window], which the cutouts read
+  hipLaunchKernelGGL(k_tail, dim3((unsigned)grid_of(4)), dim3(256), (size_t)s->look * 4, st,
+                     s->d_tail.as<TailTable>());
   hipLaunchKernelGGL(k_stage_ring, dim3((unsigned)grid_of(4)), dim3(256), 0, st, s->d_stage.as<StageTable>());
   auto kd = k_dedisp_jobs<kStreamGroups, kStreamTpw>;
   hipLaunchKernelGGL(kd, dim3((unsigned)grid_of(2)), dim3(64 * kStreamWaves), (size_t)dd_lds, st,
@@ -398,8 +417,6 @@ void launch_sequence(gsp_stream *s, int64_t dd_lds) {
   launch_search_table(ctx, s->d_series.as<SeriesTable>(), grid_of(4), s->tiling, s->musig.as<double>(),
                       s->d_widths.as<int32_t>(), (int32_t)s->widths.size(), s->wmax, s->thr, s->frags.as<Frag>(),
                       s->frag_cap, s->counter.as<unsigned long long>(), 0, st);
-  hipLaunchKernelGGL(k_tail, dim3((unsigned)grid_of(4)), dim3(256), (size_t)s->look * 4, st,
-                     s->d_tail.as<TailTable>());
   check_hip(hipGetLastError(), "launch streaming kernels");
 }
 
@@ -519,7 +536,8 @@ int64_t step_once(gsp_stream *s) {
       L.x = R.win.as<int32_t>();
       L.pitch = s->look + R.Wcap;
       L.look = s->look;
-      L.w = e - a;
+      L.w = R.last_w;  // shift out the previous window (0 for the first)
+      R.last_w = e - a;
       L.n_dm = R.n_dm;
       L.trial0 = tt.n_trials;
       tt.n_trials += R.n_dm;
@@ -598,9 +616,55 @@ int64_t step_once(gsp_stream *s) {
     }
     runs.push_back(f);
   }
+  // learned triage: cutouts from the device state of this step, network logits
+  std::vector<float> score(runs.size(), NAN);
+  if (s->cnn && !runs.empty()) {
+    const auto t_tri = Clock::now();
+    const int64_t n = (int64_t)runs.size();
+    std::vector<StreamCut> cuts((size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+      const Frag &f = runs[(size_t)k];
+      int j = 0;
+      while (j + 1 < tr.n_jobs && tr.job[j + 1].trial0 <= f.trial) ++j;
+      const JobRef &ref = series_refs[j];
+      StreamRow &R = *ref.b->rows[ref.row];
+      StreamCut &C = cuts[(size_t)k];
+      C.win = R.win.as<int32_t>();
+      C.win_pitch = s->look + R.Wcap;
+      C.a = ref.a;
+      C.mu = s->musig.as<double>() + 2 * (int64_t)tr.job[j].trial0;
+      C.ring = R.ring.as<uint16_t>();
+      C.ring_pitch = R.R + kGuard;
+      C.R = R.R;
+      C.delays = R.tables.delays_dev.as<int32_t>();
+      C.t_peak = f.e_peak - f.width + 1;
+      C.look = s->look;
+      C.n_dm = R.n_dm;
+      C.nchan = ref.b->nchan;
+      C.dm_index = f.trial - tr.job[j].trial0;
+      C.width = f.width;
+    }
+    s->d_cuts.reserve((size_t)n * sizeof(StreamCut));
+    s->d_cutimg.reserve((size_t)n * 2 * 4096 * 2);
+    s->d_logits.reserve((size_t)n * 4);
+    check_hip(hipMemcpyAsync(s->d_cuts.ptr, cuts.data(), (size_t)n * sizeof(StreamCut), hipMemcpyHostToDevice, st),
+              "copy cutout sources");
+    launch_cutouts_stream(s->d_cuts.as<StreamCut>(), n, s->d_cutimg.as<uint16_t>(), st);
+    const int rc = gsp_cnn_forward(s->cnn, s->d_cutimg.as<uint16_t>(), n, s->d_logits.as<float>(), st);
+    if (rc != GSP_OK) fail(rc, "triage network");
+    check_hip(hipMemcpyAsync(score.data(), s->d_logits.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, st), "copy scores");
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    s->scored += n;
+    s->triage_s += std::chrono::duration<double>(Clock::now() - t_tri).count();
+  }
   const auto t_done = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
-  for (const Frag &f : runs) {
+  for (size_t k = 0; k < runs.size(); ++k) {
+    const Frag &f = runs[k];
+    if (s->cnn && !(score[k] > s->triage_thr)) {  // rejected by the network
+      ++s->rejected;
+      continue;
+    }
     int j = 0;
     while (j + 1 < tr.n_jobs && tr.job[j + 1].trial0 <= f.trial) ++j;
     const JobRef &ref = series_refs[j];
@@ -619,6 +683,7 @@ int64_t step_once(gsp_stream *s) {
     c.t_last = f.t_last;
     c.snr = (float)f.snr;
     c.time_s = ((double)c.t_peak + 0.5 * (double)c.width) * (double)g.downsamp * ref.b->tsamp;
+    sc.score = score[k];
     s->out.push_back(sc);
   }
   for (auto &w : work) {
@@ -687,13 +752,13 @@ int gsp_stream_create(gsp_ctx *ctx, int64_t mem_budget_bytes, int32_t block_nsam
     std::sort(s->widths.begin(), s->widths.end());
     s->widths.erase(std::unique(s->widths.begin(), s->widths.end()), s->widths.end());
     s->wmax = s->widths.back();
-    s->look = s->wmax - 1;
+    s->look = std::max(s->wmax - 1, kCutoutReach - 1);  // boxes, and the cutouts' 64 bins of <= 8 samples
     s->thr = threshold;
     s->tiling = search_tiling(s->wmax);
     if ((int64_t)s->look * 4 > 64 * 1024) fail(GSP_EINVAL, "widths too large for the look-back shift");
     check_hip(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "create stream");
     for (DevBuf *d : {&s->d_stage, &s->d_dedisp, &s->d_series, &s->d_tail, &s->d_widths, &s->musig, &s->frags,
-                      &s->counter})
+                      &s->counter, &s->d_cuts, &s->d_cutimg, &s->d_logits})
       d->device = ctx->device;
     s->d_stage.reserve(sizeof(StageTable));
     s->d_dedisp.reserve(sizeof(DedispTable));
@@ -877,6 +942,16 @@ int gsp_stream_poll(gsp_stream *s, gsp_stream_candidate *out, int64_t cap, int64
   });
 }
 
+int gsp_stream_set_triage(gsp_stream *s, gsp_cnn *cnn, float threshold) {
+  return sguard(s, [&] {
+    if (s->running) fail(GSP_EINVAL, "the stream's worker thread is running");
+    if (cnn && !std::isfinite(threshold)) fail(GSP_EINVAL, "bad triage threshold");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cnn = cnn;
+    s->triage_thr = threshold;
+  });
+}
+
 int gsp_stream_report(gsp_stream *s, gsp_stream_stats *r) {
   return sguard(s, [&] {
     if (!r) fail(GSP_EINVAL, "null report");
@@ -898,6 +973,9 @@ int gsp_stream_report(gsp_stream *s, gsp_stream_stats *r) {
     r->busy_s = s->busy_s;
     r->mem_used = s->used;
     r->mem_budget = s->budget;
+    r->triage_scored = s->scored;
+    r->triage_rejected = s->rejected;
+    r->triage_s = s->triage_s;
     for (auto &kv : s->beams) {
       if (kv.second->admitted)
         r->beams_active += 1;
@@ -953,9 +1031,9 @@ int gsp_stream_snapshot(gsp_stream *s, int32_t beam_id, void *host_buf, int64_t 
       const size_t rb = (size_t)b.nchan * (r->R + kGuard) * 2;
       check_hip(hipMemcpy(p, r->ring.ptr, rb, hipMemcpyDeviceToHost), "copy ring");
       p += rb;
-      if (s->look) {
-        check_hip(hipMemcpy2D(p, (size_t)s->look * 4, r->win.ptr, (size_t)(s->look + r->Wcap) * 4, (size_t)s->look * 4,
-                              (size_t)r->n_dm, hipMemcpyDeviceToHost),
+      if (s->look) {  // the samples before the next window: the last `look` of [look-back | last window]
+        check_hip(hipMemcpy2D(p, (size_t)s->look * 4, r->win.as<int32_t>() + r->last_w, (size_t)(s->look + r->Wcap) * 4,
+                              (size_t)s->look * 4, (size_t)r->n_dm, hipMemcpyDeviceToHost),
                   "copy look-back");
         p += (size_t)r->n_dm * s->look * 4;
       }
@@ -985,6 +1063,7 @@ int gsp_stream_restore(gsp_stream *s, int32_t beam_id, const void *host_buf, int
     for (auto &r : b.rows) {
       r->N = get();
       r->emitted = get();
+      r->last_w = 0;  // the snapshot holds the look-back already shifted
       const size_t rb = (size_t)b.nchan * (r->R + kGuard) * 2;
       if (p + rb > end) fail(GSP_EINVAL, "snapshot truncated");
       check_hip(hipMemcpy(r->ring.ptr, p, rb, hipMemcpyHostToDevice), "copy ring");

@@ -290,17 +290,20 @@ def trial_stats(dmt, desc: DmtDesc, ctx: Context | None = None, stream=None):
 # streaming (continuous batching of beams arriving in blocks)
 # ---------------------------------------------------------------------------
 class StreamCandidate(C.Structure):
-    _fields_ = [("beam", C.c_int32), ("block", C.c_int32), ("c", Candidate)]
+    _fields_ = [("beam", C.c_int32), ("block", C.c_int32), ("c", Candidate), ("score", C.c_float),
+                ("reserved", C.c_int32)]
 
 
 class StreamStats(C.Structure):
     _fields_ = [("lat_p50_s", C.c_double), ("lat_p99_s", C.c_double), ("lat_max_s", C.c_double),
                 ("blocks", C.c_int64), ("steps", C.c_int64), ("busy_s", C.c_double), ("mem_used", C.c_int64),
                 ("mem_budget", C.c_int64), ("beams_active", C.c_int32), ("beams_queued", C.c_int32),
-                ("blocks_pending", C.c_int64)]
+                ("blocks_pending", C.c_int64), ("triage_scored", C.c_int64), ("triage_rejected", C.c_int64),
+                ("triage_s", C.c_double)]
 
 
-STREAM_CAND_DTYPE = np.dtype([("beam", np.int32), ("block", np.int32)] + [(n, CAND_DTYPE[n]) for n in CAND_DTYPE.names])
+STREAM_CAND_DTYPE = np.dtype([("beam", np.int32), ("block", np.int32)] + [(n, CAND_DTYPE[n]) for n in CAND_DTYPE.names]
+                             + [("score", np.float32), ("reserved", np.int32)])
 assert STREAM_CAND_DTYPE.itemsize == C.sizeof(StreamCandidate)
 
 _L.gsp_stream_create.restype = C.c_int
@@ -332,6 +335,8 @@ _L.gsp_stream_restore.restype = C.c_int
 _L.gsp_stream_restore.argtypes = [P, C.c_int32, P, C.c_int64]
 _L.gsp_stream_set_graph.restype = C.c_int
 _L.gsp_stream_set_graph.argtypes = [P, C.c_int]
+_L.gsp_stream_set_triage.restype = C.c_int
+_L.gsp_stream_set_triage.argtypes = [P, P, C.c_float]
 
 
 class Stream:
@@ -398,6 +403,11 @@ class Stream:
 
     def set_graph(self, on: bool):
         self._check(_L.gsp_stream_set_graph(self.h, int(bool(on))))
+
+    def set_triage(self, cnn, threshold: float = 0.0):
+        """Attach a trained Cnn (None: the plain search) scoring each step's candidates."""
+        self._triage = cnn  # keep the network alive while attached
+        self._check(_L.gsp_stream_set_triage(self.h, cnn.h if cnn is not None else None, float(threshold)))
 
     def poll(self) -> np.ndarray:
         rows = []

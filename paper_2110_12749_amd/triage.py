@@ -43,7 +43,8 @@ def match_pulses(cands: np.ndarray, w: synth.Workload) -> np.ndarray:
     channels' residual delays K |DM' - DM| (f^-2 - f_max^-2) spread over
     S = K |DM' - DM| (f_min^-2 - f_max^-2), on the early side for DM' > DM
     and the late side otherwise; the window adds 3 FWHM and the box width,
-    and the box may span up to 4 (FWHM + S) + 1 ms."""
+    and the box spans at most 2.4 (FWHM + S) + 1 ms (the best boxcar of a
+    Gaussian is 1.19 FWHM; widths are powers of two)."""
     out = np.full(len(cands), -1, np.int64)
     if not len(cands) or not w.pulses:
         return out
@@ -58,7 +59,7 @@ def match_pulses(cands: np.ndarray, w: synth.Workload) -> np.ndarray:
         lo = p.t0_s - np.where(dd > 0, span * dd, 0.0) - 3 * p.fwhm_s - box
         hi = p.t0_s + np.where(dd < 0, -span * dd, 0.0) + 3 * p.fwhm_s + box
         ok = ((np.abs(dd) <= max(2.0, 0.05 * p.dm)) & (t >= lo) & (t <= hi)
-              & (box <= 4.0 * (p.fwhm_s + span * np.abs(dd)) + 1e-3))
+              & (box <= 2.4 * (p.fwhm_s + span * np.abs(dd)) + 1e-3))
         dist = np.abs(dd)
         take = ok & (dist < best)
         out[take] = k
