@@ -111,7 +111,8 @@ def cpu_baseline(w, X, desc, every: int):
             "rtf": (w.nsamp * w.tsamp) / t_full}
 
 
-def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = None):
+def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = None, triage: str | None = None,
+                 triage_thr: float = 0.0):
     """19 beams (4096 ch, tsamp 49.152 us, lengths 2^18..2^20, per-beam ladders
     of 1000-4000 trials) streaming in blocks of 20480 samples (1.00663 s).
     Block contents come from a pool of pre-generated realistic blocks (noise
@@ -130,6 +131,11 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
     pool = [src.generate(t_begin=k * B, nrows=B) for k in range(pool_blocks)]
     ctx = gsp.Context(0)
     s = gsp.Stream(ctx, 200 << 30, B, synth.WIDTHS_512, 6.0)
+    net = None
+    if triage:  # trained network weights (gsp_cnn_save) scoring each step's candidates
+        net = gsp.Cnn(ctx)
+        net.load(triage)
+        s.set_triage(net, triage_thr)
     ids = []
     for w in beams:
         bid, ok = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
@@ -172,6 +178,8 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
     rep = s.report()
     c = s.poll()
     s.close()
+    if net is not None:
+        net.close()
     ctx.close()
     data_s = sum(min(n * B, w.nsamp) for w, n in zip(beams, nblk)) * 49.152e-6
     return {"mode": "paced (real-time arrivals)" if paced else "unpaced (all blocks at once)",
@@ -179,7 +187,10 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
             "wall_s": wall, "busy_s": rep["busy_s"], "dm_trial_samples": int(work),
             "dm_trial_samples_per_s": work / wall, "rtf_aggregate": data_s / wall,
             "lat_p50_s": rep["lat_p50_s"], "lat_p99_s": rep["lat_p99_s"], "lat_max_s": rep["lat_max_s"],
-            "block_s": period, "candidates": int(len(c))}
+            "block_s": period, "candidates": int(len(c)),
+            "triage": None if net is None else {
+                "threshold": triage_thr, "scored": int(rep["triage_scored"]), "rejected": int(rep["triage_rejected"]),
+                "ms_per_block": rep["triage_s"] / max(1, rep["blocks"]) * 1e3}}
 
 
 def main():
@@ -194,6 +205,8 @@ def main():
     ap.add_argument("--stream", choices=["paced", "unpaced"], default=None,
                     help="run the 19-beam streaming workload instead (prints its own JSON line)")
     ap.add_argument("--stream-max-blocks", type=int, default=None)
+    ap.add_argument("--triage-weights", default=None, help="stream: attach a trained network (gsp_cnn_save file)")
+    ap.add_argument("--triage-threshold", type=float, default=0.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -207,7 +220,8 @@ def main():
     from paper_2110_12749_amd import gsp
 
     if args.stream:
-        r = bench_stream(args.stream == "paced", max_blocks=args.stream_max_blocks)
+        r = bench_stream(args.stream == "paced", max_blocks=args.stream_max_blocks, triage=args.triage_weights,
+                         triage_thr=args.triage_threshold)
         print(json.dumps({"metric": METRIC, "value": r["dm_trial_samples_per_s"], "unit": "DM-trial×samples/s",
                           "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                           "dtype": "u8->int32", "data": "synthetic", "config": {"workload": "stream: 19 beams, "
