@@ -193,6 +193,47 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
                 "ms_per_block": rep["triage_s"] / max(1, rep["blocks"]) * 1e3}}
 
 
+SWEEP_SHAPES = [(4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 16), (4, 8, 4, 16), (2, 8, 8, 16), (2, 8, 4, 32),
+                (8, 4, 8, 16), (4, 4, 16, 16)]
+
+
+def shape_sweep(w):
+    """Each row of the plan alone, dedispersed with each shape (groups, trials
+    per wave, waves, channels per chunk; the library clamps the chunk to what
+    its staging registers and LDS hold): kernel time from the library's
+    event timing, mean of 2 launches after one untimed launch."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    X = w.generate()
+    fb = torch.from_numpy(X).to("cuda:0")
+    del X
+    ctx = gsp.Context(0)
+    print(f"| row | D | n_dm | requested (groups, tpw, waves, chunk) | used | ms | T adds/s |")
+    print("|---|---|---|---|---|---|---|")
+    for s, seg in enumerate(w.segments):
+        d1 = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, [seg])
+        out = torch.empty(d1.total, dtype=torch.int32, device="cuda:0")
+        adds = seg[2] * d1.n_out[0] * w.nchan
+        for c in SWEEP_SHAPES:
+            try:
+                ctx.set_row_shape(w.freqs, d1, 0, *c)
+            except gsp.GspError as e:
+                print(f"| {s} | {seg[3]} | {seg[2]} | {c} | rejected: {e} | | |", flush=True)
+                continue
+            ctx.dedisperse(fb, w.freqs, d1, out=out)
+            ctx.profile_enable(True)
+            ctx.profile_read()
+            for _ in range(2):
+                ctx.dedisperse(fb, w.freqs, d1, out=out)
+            p = ctx.profile_read()
+            ctx.profile_enable(False)
+            ms = p["dedisperse"][1] / 2
+            used = tuple(ctx.row_shape(w.freqs, d1, 0))
+            print(f"| {s} | {seg[3]} | {seg[2]} | {c} | {used} | {ms:.2f} | {adds / ms / 1e9:.2f} |", flush=True)
+        del out
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +248,8 @@ def main():
     ap.add_argument("--stream-max-blocks", type=int, default=None)
     ap.add_argument("--triage-weights", default=None, help="stream: attach a trained network (gsp_cnn_save file)")
     ap.add_argument("--triage-threshold", type=float, default=0.0)
+    ap.add_argument("--shapes", action="store_true",
+                    help="time a fixed set of dedispersion tile shapes on every row of the workload (markdown table)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -238,6 +281,9 @@ def main():
         del src, dst
 
     w = workload(args.workload)
+    if args.shapes:
+        shape_sweep(w)
+        return
     log(f"generating {w.name}: {w.nsamp} x {w.nchan}")
     t0 = time.perf_counter()
     X = w.generate()

@@ -96,7 +96,7 @@ struct SeriesJob {
   int64_t n;
   int64_t look;
   int64_t abs0;
-  int64_t tiles;   // search tiles per trial (finalize_table)
+  int64_t tiles;   // search items (segments of box ends) per trial (finalize_table)
   int64_t block0;  // first search item of the job (finalize_table)
   int32_t n_dm;
   int32_t trial0;  // global trial index of the job's first trial (finalize_table)
@@ -109,7 +109,8 @@ struct SeriesTable {
   int64_t n_items = 0;
 };
 struct SearchTiling {
-  int per = 16;     // prefix entries per thread
+  int ring = 1024;  // prefix sums kept per wave (power of two >= w_max + 512)
+  int waves = 4;    // waves per workgroup, one search item each
   int tile = 0;     // box ends per search item
   size_t lds = 0;   // dynamic LDS of the search kernel
 };

@@ -12,16 +12,17 @@
 // streaming window whose boxes may reach back into retained samples of the
 // previous window (a look-back region in front of the window).  Both kernels
 // stride over their work items, so the same code serves the per-call batch
-// launches (one item per workgroup) and the fixed-grid launches of the
+// launches (one item per workgroup or wave) and the fixed-grid launches of the
 // streaming graph.
 //
 // Both are HBM-bound streaming passes over the int32 DM-time data:
 //  k_stats  one workgroup per trial, 8 loads in flight per lane, 128-bit
 //           integer moment sums, mu and sigma finished in double;
-//  k_search one workgroup per (trial, tile of box ends): tile plus look-back
-//           loaded once, exact int64 prefix sums in LDS, an integer prefilter
-//           per width, exact double SNRs only where a box can pass, and run
-//           fragments appended with one atomic each (joined on the host).
+//  k_search one wave per (trial, segment of box ends): segment plus look-back
+//           read once, exact int64 prefix sums by wave scans into a per-wave
+//           LDS ring, an integer prefilter per width, exact double SNRs only
+//           where a box can pass, and run fragments appended with one atomic
+//           each (joined on the host).
 #include <algorithm>
 #include <vector>
 
@@ -116,7 +117,18 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const SeriesTable *__re
 // ---------------------------------------------------------------------------
 // boxcar search
 // ---------------------------------------------------------------------------
+// One wave owns one item: a trial and a segment [s0, s1) of its box ends.  It
+// walks the samples from lo = max(first valid sample, s0 - (w_max - 1)) in
+// blocks of 8 x 64: each lane holds one sample per 64-sample step, a wave-wide
+// int64 scan (DPP) plus the running carry gives the exact prefix sums P, and
+// these go into a per-wave LDS ring that keeps the last RING of them.  A box
+// (e, w) sums to P(e) - P(e - w).  Per width an integer prefilter flags the
+// box ends whose sum can reach the threshold; only those get the exact double
+// SNR.  Runs of flagged ends are followed across steps and blocks inside the
+// wave and written as fragments (one atomic each).  Waves never wait for each
+// other: there is no workgroup barrier after the widths are loaded.
 static constexpr int kSearchThreads = 256;
+static constexpr int kSearchBlock = 512;  // samples per block: 8 steps of 64
 
 __global__ void k_zero_counter(unsigned long long *c) { *c = 0ull; }
 
@@ -125,214 +137,286 @@ struct SearchArgs {
   const double *musig;
   const int32_t *widths;  // sorted, unique
   int32_t nw, wmax;
-  int32_t tile;           // box ends per workgroup (multiple of kSearchThreads)
+  int32_t tile;           // box ends per item
   float thr;
   Frag *frags;
   int64_t cap;
   unsigned long long *counter;
 };
 
-// Padded LDS index of prefix entry k: one spare slot every 16 entries, so
-// that a thread scanning 16 contiguous entries and its neighbours (16 apart)
-// hit different banks.
-__device__ __forceinline__ int qp(int k) { return k + (k >> 4); }
+// One step of the wave scan: v plus v of the lane CTRL selects (DPP), 0 where
+// the row mask or the row boundary gives no source.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int64_t add_dpp(int64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return v + (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
 
-template <int PER>
+// Inclusive scan of an int64 over the 64 lanes: shifts inside rows of 16,
+// then the row totals broadcast to the following rows.
+__device__ __forceinline__ int64_t wave_scan_i64(int64_t x) {
+  x = add_dpp<0x111, 0xf>(x);  // row_shr:1
+  x = add_dpp<0x112, 0xf>(x);  // row_shr:2
+  x = add_dpp<0x114, 0xf>(x);  // row_shr:4
+  x = add_dpp<0x118, 0xf>(x);  // row_shr:8
+  x = add_dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = add_dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ int64_t lane63(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), 63);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Per-wave LDS: the prefix ring, the prefilter bounds of the item's trial,
+// the step's exact best SNR and width per lane, and the open run.
+template <int RING>
+struct SearchWaveLds {
+  int64_t ring[RING];
+  int64_t lim[64];
+  double sb[64];
+  int32_t sk[64];
+  int64_t o_first, o_peak;
+  double o_snr;
+  int32_t o_k, o_left;
+};
+
+template <int RING>
 __global__ __launch_bounds__(kSearchThreads) void k_search(SearchArgs a) {
-  static_assert(PER % 16 == 0, "segments of 16 entries");
-  // LDS: prefix sums Q (padded), reused for the per-box-end best SNR once the
-  // sums are no longer needed; flags hold 1 + index of the best width
-  extern __shared__ int64_t Q[];
-  constexpr int kSpan = kSearchThreads * PER;
-  uint8_t *flag = reinterpret_cast<uint8_t *>(Q + kSpan + kSpan / 16 + 2);
-  double *best = reinterpret_cast<double *>(Q);
-  __shared__ int64_t wsum[kSearchThreads / 64];
-  __shared__ int64_t lim[64];
+  static_assert((RING & (RING - 1)) == 0, "ring length is a power of two");
+  extern __shared__ int64_t lds64[];
   __shared__ int32_t wsh[64];
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+  SearchWaveLds<RING> &W = reinterpret_cast<SearchWaveLds<RING> *>(lds64)[wave];
   const SeriesTable *tb = a.tb;
   const int64_t n_items = tb->n_items;
   const double thr = (double)a.thr;
+  const int nw = a.nw;
+  if ((int)threadIdx.x < nw) wsh[threadIdx.x] = a.widths[threadIdx.x];
+  __syncthreads();  // the only workgroup barrier
 
-  for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
+  for (int64_t b = (int64_t)blockIdx.x * nwaves + wave; b < n_items; b += (int64_t)gridDim.x * nwaves) {
     const SeriesJob &J = tb->job[find_job_by_item(tb, b)];
     const int64_t n = J.n;
     const int64_t local = b - J.block0;
     const int trial = (int)(local / J.tiles);
-    const int64_t tile = local - (int64_t)trial * J.tiles;
+    const int64_t seg = local - (int64_t)trial * J.tiles;
     const int g = J.trial0 + trial;
     const double mu = a.musig[2 * g], sigma = a.musig[2 * g + 1];
-    if (!(sigma > 0.0)) continue;  // uniform: the whole workgroup skips
-    // positions relative to the window's first box end
-    const int32_t *x = J.x + (int64_t)trial * J.pitch + J.e_begin;
-    const int64_t e0 = tile * a.tile;
-    const int64_t e1 = min(e0 + (int64_t)a.tile, n);
-    const int64_t lo = max(-J.look, e0 - (int64_t)(a.wmax - 1));  // may be negative (look-back)
-    const int m = (int)(e1 - lo);  // samples; Q has m + 1 entries, m <= kSpan
+    if (!(sigma > 0.0)) continue;  // uniform over the wave
+    const int32_t *x = J.x + (int64_t)trial * J.pitch + J.e_begin;  // relative positions
+    const int64_t look = J.look;
+    const int64_t s0 = seg * a.tile;
+    const int64_t s1 = min(s0 + (int64_t)a.tile, n);
+    const int64_t lo = max(-look, s0 - (int64_t)(a.wmax - 1));
+    // every box of every end in [s0, s1) starts at or after the first sample
+    const bool full = s0 - (int64_t)(a.wmax - 1) >= -look;
 
-    // widths and the integer prefilter bounds: a box can reach the
-    // threshold only if its sum is >= w mu + thr sigma sqrt(w); lim sits 2
-    // below that bound (far more than its double rounding), so every box end
-    // the exact test flags passes the prefilter
-    if (tid < a.nw) {
-      const int32_t w = a.widths[tid];
-      wsh[tid] = w;
-      const double wd = (double)w;
+    // prefilter bounds: a box can reach the threshold only if its sum is
+    // >= w mu + thr sigma sqrt(w); lim sits 2 below that bound (far more than
+    // its double rounding), so every box end the exact test flags passes
+    if (lane < nw) {
+      const double wd = (double)wsh[lane];
       const double bound = wd * mu + thr * sigma * sqrt(wd);
-      lim[tid] = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
+      W.lim[lane] = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
     }
+    if (lane == 0) W.ring[0] = 0;  // P(lo - 1)
+    __builtin_amdgcn_wave_barrier();
 
-    // ---- coalesced load: entry k+1 <- x[lo + k] ----
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int k = tid + i * kSearchThreads;
-      if (k < m) Q[qp(k + 1)] = (int64_t)x[lo + k];
-    }
-    if (tid == 0) Q[0] = 0;
-    __syncthreads();
-    // ---- exact prefix sums: each thread scans PER contiguous entries ----
-    const int k0 = tid * PER + 1;
-    int64_t run = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-      if (k0 + i <= m) run += Q[qp(k0 + i)];
-    int64_t incl = run;
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int64_t o = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += o;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int64_t acc = incl - run;
-    for (int w = 0; w < wv; ++w) acc += wsum[w];
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-      if (k0 + i <= m) {
-        acc += Q[qp(k0 + i)];
-        Q[qp(k0 + i)] = acc;
-      }
-    __syncthreads();
-
-    // ---- prefilter (integer compares), then exact SNR where it passes ----
-    // box end e (relative) uses Q[e + 1 - lo] - Q[e + 1 - w - lo]; the box
-    // must start at or after -look
-    const int len = (int)(e1 - e0);
-    const int Jn = a.tile / kSearchThreads;  // box ends per thread (<= PER)
-    const bool full = (e0 + J.look >= a.wmax - 1) && (len == a.tile);
-    int64_t qe[PER];
-    uint32_t maybe = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-      if (j < Jn) qe[j] = Q[qp((int)(min(e0 + tid + j * kSearchThreads, e1 - 1) + 1 - lo))];
-    if (full) {
-      for (int k = 0; k < a.nw; ++k) {
-        const int w = wsh[k];
-        const int64_t L = lim[k];
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-          if (j < Jn && qe[j] - Q[qp((int)(e0 + tid + j * kSearchThreads + 1 - w - lo))] >= L) maybe |= 1u << j;
-      }
-    } else {
-      for (int k = 0; k < a.nw; ++k) {
-        const int64_t w = wsh[k];
-        const int64_t L = lim[k];
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const int64_t e = e0 + tid + j * kSearchThreads;
-          if (j < Jn && e < e1 && w <= e + J.look + 1 && qe[j] - Q[qp((int)(e + 1 - w - lo))] >= L)
-            maybe |= 1u << j;
-        }
-      }
-    }
-    // exact best over widths for the box ends that passed (rare): kept in
-    // registers until the prefix sums are dead, then stored over them
-    double bs[PER];
-    uint32_t bk[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      bs[j] = 0.0;
-      bk[j] = 0;
-    }
-    if (maybe) {
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        if (!(maybe & (1u << j))) continue;
-        const int64_t e = e0 + tid + j * kSearchThreads;
-        const int64_t q1 = Q[qp((int)(e + 1 - lo))];
-        double bb = 0.0;
-        uint32_t kb = 0;
-        for (int k = 0; k < a.nw; ++k) {
-          const int64_t w = wsh[k];
-          if (w > e + J.look + 1) break;  // box would start before the first valid sample
-          const double sum = (double)(q1 - Q[qp((int)(e + 1 - w - lo))]);
-          const double snr = (sum - (double)w * mu) / (sigma * sqrt((double)w));
-          if (kb == 0 || snr > bb) {
-            bb = snr;
-            kb = (uint32_t)k + 1;
-          }
-        }
-        bs[j] = bb;
-        bk[j] = (kb != 0 && bb >= thr) ? kb : 0;
-      }
-    }
-    __syncthreads();  // prefix sums dead from here on
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int el = tid + j * kSearchThreads;
-      if (j < Jn && el < len) {
-        flag[el] = (uint8_t)bk[j];
-        if (bk[j]) best[el] = bs[j];
-      }
-    }
-    __syncthreads();
-
-    // ---- maximal runs inside the tile (argmax ties -> earlier box end) ----
-    for (int el = tid; el < len; el += kSearchThreads) {
-      if (!flag[el]) continue;
-      if (el > 0 && flag[el - 1]) continue;  // not a run start
-      int pk = el;
-      double ps = best[el];
-      int kk = el + 1;
-      for (; kk < len && flag[kk]; ++kk)
-        if (best[kk] > ps) {
-          ps = best[kk];
-          pk = kk;
-        }
+    bool open = false;
+    int64_t o_first = 0, o_peak = 0, o_last = 0;
+    double o_snr = 0.0;
+    int o_k = 0, o_left = 0;
+    auto emit = [&](int64_t t_first, int64_t t_last, int64_t e_peak, double snr, int k, int left, int right) {
       const unsigned long long idx = atomicAdd(a.counter, 1ull);
       if ((int64_t)idx < a.cap) {
         Frag f;
         f.trial = g;
-        f.width = wsh[flag[pk] - 1];
-        f.t_first = J.abs0 + e0 + el;
-        f.t_last = J.abs0 + e0 + kk - 1;
-        f.e_peak = J.abs0 + e0 + pk;
-        f.snr = ps;
-        f.open_left = (el == 0 && e0 > 0) ? 1 : 0;
-        f.open_right = (kk == len && e1 < n) ? 1 : 0;
+        f.width = wsh[k - 1];
+        f.t_first = J.abs0 + t_first;
+        f.t_last = J.abs0 + t_last;
+        f.e_peak = J.abs0 + e_peak;
+        f.snr = snr;
+        f.open_left = left;
+        f.open_right = right;
         a.frags[idx] = f;
       }
+    };
+
+    const int64_t count = s1 - lo;
+    const int64_t nblk = (count + kSearchBlock - 1) / kSearchBlock;
+    // samples in flight: the next block's 8 per lane (indices clamped into
+    // [lo, s1 - 1], so every load stays inside the series)
+    int32_t vn[8];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) vn[it] = x[min(lo + 64 * it + lane, s1 - 1)];
+    int64_t carry = 0;
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+      const int64_t eb = lo + blk * kSearchBlock;  // position of lane 0, step 0
+      int32_t v[8];
+#pragma unroll
+      for (int it = 0; it < 8; ++it) v[it] = vn[it];
+      if (blk + 1 < nblk) {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) vn[it] = x[min(eb + kSearchBlock + 64 * it + lane, s1 - 1)];
+      }
+      // ---- exact prefix sums into the ring ----
+      const int r0 = (int)(eb - lo + 1);
+      int64_t P[8];
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int64_t e = eb + 64 * it + lane;
+        P[it] = carry + wave_scan_i64(e < s1 ? (int64_t)v[it] : 0);
+        carry = lane63(P[it]);
+        W.ring[(r0 + 64 * it + lane) & (RING - 1)] = P[it];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (eb + kSearchBlock - 1 < s0) continue;  // look-back block: sums only
+
+      // ---- integer prefilter, widths outer ----
+      uint32_t mbits = 0;
+      for (int k = 0; k < nw; ++k) {
+        const int w = wsh[k];
+        const int64_t L = W.lim[k];
+        const int rw = r0 + lane - w;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int64_t e = eb + 64 * it + lane;
+          const int64_t q = W.ring[(rw + 64 * it) & (RING - 1)];
+          const bool ok = e >= s0 && e < s1 && (full || (int64_t)w <= e + look + 1);
+          if (ok && P[it] - q >= L) mbits |= 1u << it;
+        }
+      }
+
+      // ---- exact SNR and runs, step by step ----
+#pragma unroll 1
+      for (int it = 0; it < 8; ++it) {
+        const int64_t e0 = eb + 64 * it;
+        const int64_t e = e0 + lane;
+        const bool maybe = (mbits >> it) & 1u;
+        if (__ballot(maybe) == 0ull && !open) continue;
+        bool fl = false;
+        double bs = 0.0;
+        int kb = 0;
+        if (maybe) {
+          const int re = (int)(e - lo + 1);
+          const int64_t q1 = W.ring[re & (RING - 1)];
+          for (int k = 0; k < nw; ++k) {
+            const int w = wsh[k];
+            if ((int64_t)w > e + look + 1) break;  // box would start before the first sample
+            const double sum = (double)(q1 - W.ring[(re - w) & (RING - 1)]);
+            const double snr = (sum - (double)w * mu) / (sigma * sqrt((double)w));
+            if (kb == 0 || snr > bs) {
+              bs = snr;
+              kb = k + 1;
+            }
+          }
+          fl = kb != 0 && bs >= thr;
+        }
+        const uint64_t m = __ballot(fl);
+        if (open && !(m & 1ull)) {  // the open run ended on the previous step
+          if (lane == 0) emit(o_first, o_last, o_peak, o_snr, o_k, o_left, 0);
+          open = false;
+        }
+        if (m == 0ull) continue;
+        W.sb[lane] = bs;
+        W.sk[lane] = kb;
+        __builtin_amdgcn_wave_barrier();
+        const bool last_step = e0 + 63 >= s1 - 1;  // the segment's last box end is on this step
+        const bool start = fl && (lane == 0 || !((m >> (lane - 1)) & 1ull));
+        if (start) {
+          int l = lane, pk = lane;
+          double ps = bs;
+          while (l + 1 < 64 && ((m >> (l + 1)) & 1ull)) {
+            ++l;
+            const double s = W.sb[l];
+            if (s > ps) {  // ties keep the earlier box end
+              ps = s;
+              pk = l;
+            }
+          }
+          int64_t f_first = e0 + lane, f_peak = e0 + pk;
+          double f_snr = ps;
+          int f_k = W.sk[pk];
+          int f_left = (f_first == s0 && s0 > 0) ? 1 : 0;
+          if (lane == 0 && open) {  // continues the open run
+            f_first = o_first;
+            f_left = o_left;
+            if (!(ps > o_snr)) {
+              f_peak = o_peak;
+              f_snr = o_snr;
+              f_k = o_k;
+            }
+          }
+          if (l == 63 && !last_step) {  // still open: hand over to the next step
+            W.o_first = f_first;
+            W.o_peak = f_peak;
+            W.o_snr = f_snr;
+            W.o_k = f_k;
+            W.o_left = f_left;
+          } else {
+            const int64_t f_last = e0 + l;
+            emit(f_first, f_last, f_peak, f_snr, f_k, f_left, (f_last == s1 - 1 && s1 < n) ? 1 : 0);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        open = ((m >> 63) & 1ull) && !last_step;
+        if (open) {
+          o_first = W.o_first;
+          o_peak = W.o_peak;
+          o_snr = W.o_snr;
+          o_k = W.o_k;
+          o_left = W.o_left;
+          o_last = e0 + 63;
+        }
+      }
     }
-    __syncthreads();  // LDS reused by the next item
+    if (open && lane == 0) emit(o_first, o_last, o_peak, o_snr, o_k, o_left, (o_last == s1 - 1 && s1 < n) ? 1 : 0);
+    __builtin_amdgcn_wave_barrier();  // per-wave LDS reused by the next item
   }
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+static const void *search_kernel(int ring) {
+  switch (ring) {
+    case 1024: return (const void *)k_search<1024>;
+    case 2048: return (const void *)k_search<2048>;
+    case 4096: return (const void *)k_search<4096>;
+    case 8192: return (const void *)k_search<8192>;
+    default: return (const void *)k_search<16384>;
+  }
+}
+
 void set_search_attributes(const SearchTiling &tl) {
-  const void *k = tl.per == 16 ? (const void *)k_search<16> : (const void *)k_search<32>;
-  check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl.lds), "set search LDS size");
+  check_hip(hipFuncSetAttribute(search_kernel(tl.ring), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl.lds),
+            "set search LDS size");
 }
 
 SearchTiling search_tiling(int32_t max_width) {
   SearchTiling t;
-  t.per = max_width <= 2049 ? 16 : 32;
-  const int span = kSearchThreads * t.per;
-  const int look = (max_width - 1 + kSearchThreads - 1) / kSearchThreads * kSearchThreads;
-  t.tile = span - look;
-  if (t.tile < kSearchThreads) fail(GSP_EINVAL, "widths too large for the search tile");
-  t.lds = sizeof(int64_t) * (size_t)(span + span / 16 + 2) + (size_t)span;
+  // the ring holds the sums of one block plus w_max before it
+  t.ring = 1024;
+  while (t.ring < max_width + kSearchBlock) t.ring *= 2;
+  if (t.ring > 16384) fail(GSP_EINVAL, "widths too large for the search ring");
+  size_t per_wave = 0;
+  switch (t.ring) {
+    case 1024: per_wave = sizeof(SearchWaveLds<1024>); break;
+    case 2048: per_wave = sizeof(SearchWaveLds<2048>); break;
+    case 4096: per_wave = sizeof(SearchWaveLds<4096>); break;
+    case 8192: per_wave = sizeof(SearchWaveLds<8192>); break;
+    default: per_wave = sizeof(SearchWaveLds<16384>); break;
+  }
+  t.waves = (int)std::max<size_t>(1, std::min<size_t>(kSearchThreads / 64, (size_t)(128 * 1024) / per_wave));
+  t.lds = per_wave * (size_t)t.waves;
+  // long segments keep the look-back re-read small; at least 16 blocks
+  t.tile = std::max(8192, ((max_width - 1) / kSearchBlock + 1) * kSearchBlock * 16);
   return t;
 }
 
@@ -378,10 +462,14 @@ void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, 
   if (grid <= 0) return;
   if (grid >= (1LL << 31)) fail(GSP_EOVERFLOW, "too many search workgroups");
   ProfScope prof(ctx, "search", st, bytes);
-  if (tl.per == 16)
-    hipLaunchKernelGGL(k_search<16>, dim3((unsigned)grid), dim3(kSearchThreads), tl.lds, st, a);
-  else
-    hipLaunchKernelGGL(k_search<32>, dim3((unsigned)grid), dim3(kSearchThreads), tl.lds, st, a);
+  const dim3 blk((unsigned)(64 * tl.waves));
+  switch (tl.ring) {
+    case 1024: hipLaunchKernelGGL(k_search<1024>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+    case 2048: hipLaunchKernelGGL(k_search<2048>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+    case 4096: hipLaunchKernelGGL(k_search<4096>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+    case 8192: hipLaunchKernelGGL(k_search<8192>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+    default: hipLaunchKernelGGL(k_search<16384>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+  }
   check_hip(hipGetLastError(), "launch search kernel");
 }
 
@@ -432,7 +520,7 @@ void launch_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, c
   SeriesTable *d = upload_table(ctx, t, st);
   set_search_attributes(tl);
   // bytes: the int32 DM-time array read once (look-back overlap not counted)
-  launch_search_table(ctx, d, t.n_items, tl, stats_musig(ctx, desc), widths_dev, n_widths, max_width, thr, frags,
+  launch_search_table(ctx, d, (t.n_items + tl.waves - 1) / tl.waves, tl, stats_musig(ctx, desc), widths_dev, n_widths, max_width, thr, frags,
                       cap, counter, 4.0 * (double)desc->total, st);
 }
 

@@ -310,3 +310,40 @@ def triage_beam(k: int, split: str = "train", nsamp: int = 1 << 17, n_pulses: in
     for _ in range(n_spikes):
         w.spikes.append((int(rng.integers(0, nsamp - 4)), int(rng.integers(1, 4)), 40.0))
     return _with_amps(w)
+
+
+def search_cases(n: int = 30000, seed: int = 0) -> np.ndarray:
+    """Hand-shaped int32 series [trials][n] for the boxcar search alone (no
+    dedispersion): noise of sigma 1000 around 10^6 plus, per trial,
+      0  noise only;
+      1  a +3 sigma plateau over samples 5000-24999 (one run across many
+         segments and blocks) and a bright spike on it;
+      2  a noise-free +6 sigma shelf over 990-1019 carrying two equal spikes
+         at 1000 and 1006 (equal box sums: a tie inside one run), and spikes
+         at the first and last sample and on both sides of 8192;
+      3  the same shapes around 2^30 with sigma 2^20 (sums beyond 2^32);
+      4  a constant (sigma 0: no candidates);
+      5  negative values (noise around -10^6) with a one-sample pulse every
+         2500 samples;
+      6  a wide Gaussian pulse (FWHM 300) next to a narrow one.
+    """
+    rng = np.random.default_rng([BASE_SEED + 9, seed])
+    x = np.rint(1e6 + 1000.0 * rng.standard_normal((7, n))).astype(np.int64)
+    x[1, 5000:25000] += 3000
+    x[1, 15000 % n] += 60000
+    for i, (base, sig) in ((2, (1e6, 1000)), (3, (float(1 << 30), float(1 << 20)))):
+        if i == 3:
+            x[i] = np.rint(base + sig * rng.standard_normal(n)).astype(np.int64)
+        x[i, 990:1020] = int(base + 6 * sig)
+        x[i, [t for t in (1000, 1006) if t < n]] += int(40 * sig)
+        for t in (0, 8191, 8192, n - 1):
+            if t < n:
+                x[i, t] += int(40 * sig)
+    x[4] = 123456
+    x[5] = np.rint(-1e6 + 1000.0 * rng.standard_normal(n)).astype(np.int64)
+    x[5, ::2500] += 20000
+    t = np.arange(n)
+    x[6] += np.rint(800.0 * np.exp(-0.5 * ((t - 12000) / (300 / 2.355)) ** 2)).astype(np.int64)
+    x[6, 12500 % n] += 30000
+    assert np.abs(x).max() < 2 ** 31
+    return x.astype(np.int32)

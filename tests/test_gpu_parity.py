@@ -105,15 +105,14 @@ def test_saturated_input_no_overflow(env):
     assert len(ctx.single_pulse_search(dmt, desc, [1, 2, 4], 3.0)) == 0
 
 
-def test_realistic_full_size_sampled(env):
-    """The realistic workload (4096 ch, 2^20 samples, 3850 trials) at full
-    size: sampled outputs of every row bit-exact, and whole-row searches of
-    selected trials (including the trials of injected pulses) matched."""
+def _full_size_sampled(env, w):
+    """Sampled outputs of every row bit-exact (corners + 300 random points
+    per row), and whole-row searches of selected trials (the trials of 3
+    injected pulses and a low-DM trial) matched against the oracle."""
     gsp, ctx, torch = env
-    w = synth.realistic()
-    say("[case] realistic full size: generate")
+    say(f"[case] {w.name} full size: generate")
     X, desc, dmt = _run(env, w)
-    say("[case] realistic: sampled points")
+    say(f"[case] {w.name}: sampled points")
     rng = np.random.default_rng(1)
     views = gsp.segment_views(desc, dmt)
     for s, seg in enumerate(w.segments):
@@ -123,9 +122,9 @@ def test_realistic_full_size_sampled(env):
         ref = oracle.dedisperse_points(X, w.freqs, w.tsamp, seg, tr, tt)
         got = views[s][torch.from_numpy(tr).long().cuda(), torch.from_numpy(tt).long().cuda()].cpu().numpy()
         assert (got.astype(np.int64) == ref).all(), f"row {s}"
-    say("[case] realistic: search of selected trials")
+    say(f"[case] {w.name}: search of selected trials")
     cg = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold)
-    # the trial closest to each of 3 pulses, plus a noise-only trial
+    # the trial closest to each of 3 pulses, plus a low-DM trial
     picks = []
     for p in w.pulses[:3]:
         for s, (lo, st, n, D) in enumerate(w.segments):
@@ -137,10 +136,22 @@ def test_realistic_full_size_sampled(env):
     for s, i in picks:
         say(f"  oracle row {s} trial {i}")
         row = oracle.dedisperse_segment(X, w.freqs, w.tsamp, w.segments[s], trials=(i, i + 1))
-        mu, sg = oracle.stats(row[0])
         co = oracle_cands_with_seg([(s, oracle.search_series(row[0], w.widths, w.threshold, trial=i))])
         sel = cg[(cg["seg"] == s) & (cg["dm_index"] == i)]
         match_candidates(sel, co, w.threshold)
         say(f"  row {s} trial {i}: gpu {len(sel)} oracle {len(co)}")
     del dmt
     torch.cuda.empty_cache()
+
+
+def test_realistic_full_size_sampled(env):
+    """The realistic workload (4096 ch over 1000-1500 MHz, 2^20 samples, 3850
+    trials in 4 rows) at full size."""
+    _full_size_sampled(env, synth.realistic())
+
+
+def test_wideband_full_size_sampled(env):
+    """The wideband large-delay workload (4096 ch over 270-1620 MHz, 2^19
+    samples, 3350 trials, maximum delay 84,250 samples at D = 4, RFI bursts
+    and zero-DM spikes) at full size."""
+    _full_size_sampled(env, synth.wideband())
