@@ -254,8 +254,8 @@ def main():
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path (beams or DM ranges would shard "
-            "across GPUs with no exchange step; see DESIGN.md).  Run with --gpus 1.")
+        log("bench.py measures one GPU only: the library has no multi-GPU path (beams or DM ranges would shard "
+            "across GPUs with no exchange step).  Run with --gpus 1.")
         sys.exit(2)
 
     import numpy as np

@@ -165,18 +165,18 @@ __device__ __forceinline__ int64_t wave_scan_i64(int64_t x) {
   return x;
 }
 
-__device__ __forceinline__ int64_t lane63(int64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), 63);
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+__device__ __forceinline__ int64_t lane63(int64_t v) { return readlane_i64(v, 63); }
 
-// Per-wave LDS: the prefix ring, the prefilter bounds of the item's trial,
-// the step's exact best SNR and width per lane, and the open run.
+// Per-wave LDS: the prefix ring, the step's exact best SNR and width per
+// lane, and the open run.
 template <int RING>
 struct SearchWaveLds {
   int64_t ring[RING];
-  int64_t lim[64];
   double sb[64];
   int32_t sk[64];
   int64_t o_first, o_peak;
@@ -184,8 +184,10 @@ struct SearchWaveLds {
   int32_t o_k, o_left;
 };
 
+// Four waves per SIMD (at most 128 VGPRs): occupancy hides the LDS and
+// memory latency better than the registers a lower occupancy would free.
 template <int RING>
-__global__ __launch_bounds__(kSearchThreads) void k_search(SearchArgs a) {
+__global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_search(SearchArgs a) {
   static_assert((RING & (RING - 1)) == 0, "ring length is a power of two");
   extern __shared__ int64_t lds64[];
   __shared__ int32_t wsh[64];
@@ -220,10 +222,15 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(SearchArgs a) {
     // prefilter bounds: a box can reach the threshold only if its sum is
     // >= w mu + thr sigma sqrt(w); lim sits 2 below that bound (far more than
     // its double rounding), so every box end the exact test flags passes
+    // (lane k holds width k and its bound; the loops below read them with
+    // readlane, so they cost no LDS round trip)
+    int lane_w = 0;
+    int64_t lane_lim = INT64_MAX;
     if (lane < nw) {
-      const double wd = (double)wsh[lane];
+      lane_w = wsh[lane];
+      const double wd = (double)lane_w;
       const double bound = wd * mu + thr * sigma * sqrt(wd);
-      W.lim[lane] = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
+      lane_lim = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
     }
     if (lane == 0) W.ring[0] = 0;  // P(lo - 1)
     __builtin_amdgcn_wave_barrier();
@@ -278,19 +285,40 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(SearchArgs a) {
       __builtin_amdgcn_wave_barrier();
       if (eb + kSearchBlock - 1 < s0) continue;  // look-back block: sums only
 
-      // ---- integer prefilter, widths outer ----
-      uint32_t mbits = 0;
-      for (int k = 0; k < nw; ++k) {
-        const int w = wsh[k];
-        const int64_t L = W.lim[k];
-        const int rw = r0 + lane - w;
+      // ---- integer prefilter, widths outer: per width the 8 ring reads are
+      // issued together; each compare leaves a wave mask ----
+      uint64_t mk[8];
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int64_t e = eb + 64 * it + lane;
-          const int64_t q = W.ring[(rw + 64 * it) & (RING - 1)];
-          const bool ok = e >= s0 && e < s1 && (full || (int64_t)w <= e + look + 1);
-          if (ok && P[it] - q >= L) mbits |= 1u << it;
+      for (int it = 0; it < 8; ++it) mk[it] = 0;
+      if (full) {
+        for (int k = 0; k < nw; ++k) {
+          const int w = __builtin_amdgcn_readlane(lane_w, k);
+          const int64_t L = readlane_i64(lane_lim, k);
+          const int bw = r0 + lane - w;
+          int64_t qv[8];
+#pragma unroll
+          for (int it = 0; it < 8; ++it) qv[it] = W.ring[(bw + 64 * it) & (RING - 1)];
+#pragma unroll
+          for (int it = 0; it < 8; ++it) mk[it] |= __ballot(P[it] - qv[it] >= L);
         }
+      } else {
+        for (int k = 0; k < nw; ++k) {
+          const int w = __builtin_amdgcn_readlane(lane_w, k);
+          const int64_t L = readlane_i64(lane_lim, k);
+          const int bw = r0 + lane - w;
+          int64_t qv[8];
+#pragma unroll
+          for (int it = 0; it < 8; ++it) qv[it] = W.ring[(bw + 64 * it) & (RING - 1)];
+#pragma unroll
+          for (int it = 0; it < 8; ++it)
+            mk[it] |= __ballot((P[it] - qv[it] >= L) & ((int64_t)w <= eb + 64 * it + lane + look + 1));
+        }
+      }
+      uint32_t mbits = 0;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int64_t e = eb + 64 * it + lane;
+        mbits |= (uint32_t)(((mk[it] >> lane) & 1ull) & (e >= s0) & (e < s1)) << it;
       }
 
       // ---- exact SNR and runs, step by step ----
@@ -389,8 +417,7 @@ static const void *search_kernel(int ring) {
     case 1024: return (const void *)k_search<1024>;
     case 2048: return (const void *)k_search<2048>;
     case 4096: return (const void *)k_search<4096>;
-    case 8192: return (const void *)k_search<8192>;
-    default: return (const void *)k_search<16384>;
+    default: return (const void *)k_search<8192>;
   }
 }
 
@@ -404,14 +431,13 @@ SearchTiling search_tiling(int32_t max_width) {
   // the ring holds the sums of one block plus w_max before it
   t.ring = 1024;
   while (t.ring < max_width + kSearchBlock) t.ring *= 2;
-  if (t.ring > 16384) fail(GSP_EINVAL, "widths too large for the search ring");
+  if (t.ring > 8192) fail(GSP_EINVAL, "widths too large for the search ring (at most 7680)");
   size_t per_wave = 0;
   switch (t.ring) {
     case 1024: per_wave = sizeof(SearchWaveLds<1024>); break;
     case 2048: per_wave = sizeof(SearchWaveLds<2048>); break;
     case 4096: per_wave = sizeof(SearchWaveLds<4096>); break;
-    case 8192: per_wave = sizeof(SearchWaveLds<8192>); break;
-    default: per_wave = sizeof(SearchWaveLds<16384>); break;
+    default: per_wave = sizeof(SearchWaveLds<8192>); break;
   }
   t.waves = (int)std::max<size_t>(1, std::min<size_t>(kSearchThreads / 64, (size_t)(128 * 1024) / per_wave));
   t.lds = per_wave * (size_t)t.waves;
@@ -467,8 +493,7 @@ void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, 
     case 1024: hipLaunchKernelGGL(k_search<1024>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
     case 2048: hipLaunchKernelGGL(k_search<2048>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
     case 4096: hipLaunchKernelGGL(k_search<4096>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
-    case 8192: hipLaunchKernelGGL(k_search<8192>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
-    default: hipLaunchKernelGGL(k_search<16384>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
+    default: hipLaunchKernelGGL(k_search<8192>, dim3((unsigned)grid), blk, tl.lds, st, a); break;
   }
   check_hip(hipGetLastError(), "launch search kernel");
 }
