@@ -61,6 +61,12 @@ struct GemmArgs {
   int32_t out_bf16;        // 1: store bf16, 0: store fp32
   int32_t accumulate;      // fp32 output only: C += result
   int32_t k_chunk;         // split-K: workgroup z covers k in [z*k_chunk, (z+1)*k_chunk); atomic fp32 adds
+  // implicit im2col (3x3, padding 1) for A when im_x is set: A[m][k] =
+  // x(n, c, h + dh, w + dw) with m = (n*H + h)*H + w, k = tap*C + c,
+  // tap = (dh+1)*3 + (dw+1); x addressed with strides (n, c, h, w)
+  const uint16_t *im_x;
+  int64_t im_sn, im_sc, im_sh, im_sw;
+  int32_t im_C, im_H;
 };
 
 static constexpr int kTM = 64, kTN = 64, kTK = 16;
@@ -82,6 +88,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  // implicit im2col: the pixel of each of this thread's 4 A rows, once
+  const uint16_t *im_base[4];
+  int im_h[4], im_w[4];
+  if (g.im_x) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t m = min(m0 + (tid + u * 256) / kTK, (int64_t)g.M - 1);
+      const int HH = g.im_H * g.im_H;
+      const int64_t n = m / HH;
+      const int hw = (int)(m - n * HH);
+      im_h[u] = hw / g.im_H;
+      im_w[u] = hw - im_h[u] * g.im_H;
+      im_base[u] = g.im_x + n * g.im_sn;
+    }
+  }
   for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
     // stage A (64 x 16) and B (16 x 64): 4 elements of each per thread
 #pragma unroll
@@ -90,7 +111,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       const int r = e / kTK, c = e % kTK;
       const int64_t m = m0 + r;
       const int k = k0 + c;
-      As[r][c] = (m < g.M && k < k_end) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+      if (g.im_x) {
+        uint16_t v = 0;
+        if (m < g.M && k < k_end) {
+          const int tap = k / g.im_C, ch = k - tap * g.im_C;
+          const int hh = im_h[u] + tap / 3 - 1, ww = im_w[u] + tap % 3 - 1;
+          if (hh >= 0 && hh < g.im_H && ww >= 0 && ww < g.im_H)
+            v = im_base[u][ch * g.im_sc + hh * g.im_sh + ww * g.im_sw];
+        }
+        As[r][c] = v;
+      } else {
+        As[r][c] = (m < g.M && k < k_end) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
+      }
       const int kr = e / kTN, nc = e % kTN;
       const int64_t n = n0 + nc;
       const int kb = k0 + kr;
@@ -300,6 +332,22 @@ struct CutoutArgs {
   uint16_t *out;  // bf16 [n][2][64][64]
 };
 
+// Sum of a uint32 over the 64 lanes of a wave (DPP shifts inside rows of 16,
+// then row totals broadcast down), returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t add_dpp_u32(uint32_t v) {
+  return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x = add_dpp_u32<0x111, 0xf>(x);  // row_shr:1
+  x = add_dpp_u32<0x112, 0xf>(x);  // row_shr:2
+  x = add_dpp_u32<0x114, 0xf>(x);  // row_shr:4
+  x = add_dpp_u32<0x118, 0xf>(x);  // row_shr:8
+  x = add_dpp_u32<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = add_dpp_u32<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // One workgroup per candidate.  Box end e = t_peak + width - 1 (row
 // resolution), bin width r = clamp(width / 8, 1, rmax); bin b covers samples
 // e - (64 - b) r + 1 .. e - (63 - b) r, so the box fills the last ~8 bins and
@@ -324,45 +372,66 @@ __device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = max(1, min(rmax, width / 8));
   const int lo = max(0, min(dm_index - 32, n_dm - 64));
-  // ---- DM-time ----
-  for (int u = tid; u < 64 * 64; u += 256) {
-    const int q = u / 64, b = u % 64;
-    const int tr = lo + q;
-    double v = 0.0;
-    if (tr < n_dm) {
-      const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
-      for (int j = 0; j < r; ++j) {
-        const int64_t t = t0 + j;
-        v += t >= 0 ? (double)dm(tr, t) : mean(tr);
+  // ---- DM-time: 16 pixels per thread, their loads issued together ----
+  {
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = 0.0;
+    for (int j = 0; j < r; ++j) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int u = tid + 256 * i;
+        const int tr = lo + u / 64, b = u % 64;
+        const int64_t t = e - (int64_t)(64 - b) * r + 1 + j;
+        if (tr < n_dm) v[i] += t >= 0 ? (double)dm(tr, t) : mean(tr);
       }
     }
-    img[0][u] = v;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) img[0][tid + 256 * i] = v[i];
   }
   // ---- frequency-time: one wave per band, lanes over the band's channels ----
+  // Every lane sums its channels' samples of all 64 bins (exact integers,
+  // all loads of one sample offset in flight together); the band's bin sums
+  // are then reduced over the lanes and bin b lands on lane b.
   for (int band = wave; band < 64; band += 4) {
     const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
-    double valid_sum = 0.0;
-    int n_valid_bins = 0;
-    for (int b = 0; b < 64; ++b) {
-      const int64_t t0 = e - (int64_t)(64 - b) * r + 1;
-      double acc = 0.0;
-      for (int ch = cb + lane; ch < ce; ch += 64)
-        for (int j = 0; j < r; ++j)
-          if (t0 + j >= 0) acc += (double)ft(ch, t0 + j);
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      const int64_t first = max((int64_t)0, t0);
-      const int cnt = (int)max((int64_t)0, t0 + r - first);
-      const double v = cnt > 0 ? acc * (double)r / (double)cnt : NAN;
-      if (cnt > 0) {
-        valid_sum += v;
-        ++n_valid_bins;
+    uint32_t acc[64];
+#pragma unroll
+    for (int b = 0; b < 64; ++b) acc[b] = 0;
+    for (int ch = cb + lane; ch < ce; ch += 64)
+      for (int j = 0; j < r; ++j) {
+#pragma unroll
+        for (int b = 0; b < 64; ++b) {
+          const int64_t t = e - (int64_t)(64 - b) * r + 1 + j;
+          if (t >= 0) acc[b] += ft(ch, t);
+        }
       }
-      if (lane == 0) img[1][band * 64 + b] = v;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int b = 0; b < 64; ++b) {
+      const uint32_t tot = wave_sum_u32(acc[b]);
+      if (lane == b) mine = tot;
     }
-    if (lane == 0 && n_valid_bins < 64) {
-      const double fill = n_valid_bins ? valid_sum / n_valid_bins : 0.0;
-      for (int b = 0; b < 64; ++b)
-        if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
+    const int64_t t0 = e - (int64_t)(64 - lane) * r + 1;
+    const int64_t first = max((int64_t)0, t0);
+    const int cnt = (int)max((int64_t)0, t0 + r - first);
+    // a bin partly before the start is scaled up to r samples; one wholly
+    // before it is filled below with the mean of the band's valid bins
+    img[1][band * 64 + lane] = cnt > 0 ? (double)mine * (double)r / (double)cnt : NAN;
+    if (__ballot(cnt == 0) != 0ull) {
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) {
+        double valid_sum = 0.0;
+        int n_valid = 0;
+        for (int b = 0; b < 64; ++b)
+          if (!isnan(img[1][band * 64 + b])) {
+            valid_sum += img[1][band * 64 + b];
+            ++n_valid;
+          }
+        const double fill = n_valid ? valid_sum / n_valid : 0.0;
+        for (int b = 0; b < 64; ++b)
+          if (isnan(img[1][band * 64 + b])) img[1][band * 64 + b] = fill;
+      }
     }
   }
   __syncthreads();
@@ -579,8 +648,10 @@ GemmArgs ga(const uint16_t *A, int64_t am, int64_t ak, const uint16_t *B, int64_
   return g;
 }
 
-// Forward pass of a batch; logits (fp32) left in c->z.
-void forward(gsp_cnn *c, const uint16_t *x, int64_t n, hipStream_t st) {
+// Forward pass of a batch; logits (fp32) left in c->z.  With keep_col the
+// im2col matrices are written out for the backward pass; without, the
+// convolutions gather their inputs inside the GEMM (same values, same sums).
+void forward(gsp_cnn *c, const uint16_t *x, int64_t n, hipStream_t st, bool keep_col) {
   const uint16_t *wb = c->pbf.as<uint16_t>();
   const float *p = c->p32.as<float>();
   const uint16_t *in = x;
@@ -589,9 +660,19 @@ void forward(gsp_cnn *c, const uint16_t *x, int64_t n, hipStream_t st) {
     const ConvSpec &cs = kConv[l];
     const int H = cs.h;
     const int64_t M = n * H * H, K = 9 * cs.cin;
-    hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, in, sn, sc, sh, sw, (int)n, cs.cin, H, H,
-                       c->col[l].as<uint16_t>());
     GemmArgs g = ga(c->col[l].as<uint16_t>(), K, 1, wb + c->L.w[l], 1, K, c->act[l].ptr, cs.cout, 1, M, cs.cout, K);
+    if (keep_col) {
+      hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, in, sn, sc, sh, sw, (int)n, cs.cin, H, H,
+                         c->col[l].as<uint16_t>());
+    } else {
+      g.im_x = in;
+      g.im_sn = sn;
+      g.im_sc = sc;
+      g.im_sh = sh;
+      g.im_sw = sw;
+      g.im_C = cs.cin;
+      g.im_H = H;
+    }
     g.bias = p + c->L.b[l];
     g.relu = 1;
     g.out_bf16 = 1;
@@ -769,7 +850,7 @@ int gsp_cnn_forward(gsp_cnn *c, const uint16_t *x, int64_t n, float *logits, voi
     hipStream_t st = static_cast<hipStream_t>(stream);
     check_hip(hipStreamSynchronize(st), "synchronise stream");
     reserve_batch(c, n);
-    forward(c, x, n, st);
+    forward(c, x, n, st, false);
     c->last_n = n;
     check_hip(hipMemcpyAsync(logits, c->z.ptr, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "copy logits");
   });
@@ -783,7 +864,7 @@ int gsp_cnn_gradients(gsp_cnn *c, const uint16_t *x, const float *labels, int64_
     hipStream_t st = static_cast<hipStream_t>(stream);
     check_hip(hipStreamSynchronize(st), "synchronise stream");
     reserve_batch(c, n);
-    forward(c, x, n, st);
+    forward(c, x, n, st, true);
     c->last_n = n;
     backward(c, labels, n, st);
     std::vector<float> loss((size_t)n);
@@ -807,7 +888,7 @@ int gsp_cnn_train_step(gsp_cnn *c, const uint16_t *x, const float *labels, int64
     hipStream_t st = static_cast<hipStream_t>(stream);
     check_hip(hipStreamSynchronize(st), "synchronise stream");
     reserve_batch(c, n);
-    forward(c, x, n, st);
+    forward(c, x, n, st, true);
     c->last_n = n;
     backward(c, labels, n, st);
     c->t += 1;
