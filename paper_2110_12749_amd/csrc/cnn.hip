@@ -328,6 +328,7 @@ struct CutoutArgs {
   const gsp_candidate *cand;
   int64_t n;
   int32_t nchan, n_seg, rmax;
+  int32_t tiled;      // bands are 16-byte aligned row segments (nchan % 1024 == 0, fb 16-byte aligned)
   CutRow row[GSP_MAX_SEG];
   uint16_t *out;  // bf16 [n][2][64][64]
 };
@@ -366,9 +367,12 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
 //   ft(c, t)   channel c's downsampled sample t >= 0 shifted by its delay at
 //              the candidate's trial (t + d_c);
 // img: LDS [2][4096] doubles, red: LDS [3][256]; out: bf16 [2][4096].
-template <class DM, class MEAN, class FT>
+// band(band, cb, ce, e, r, mine): an optional faster way to the band's bin
+// sums (bin b on lane b, every lane of the wave calls it); returns false where
+// it does not apply, and the loads below run instead.
+template <class DM, class MEAN, class FT, class BAND>
 __device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int nchan, int rmax, DM dm, MEAN mean,
-                              FT ft, double (*img)[4096], double (*red)[256], uint16_t *out) {
+                              FT ft, BAND band_sums, double (*img)[4096], double (*red)[256], uint16_t *out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = max(1, min(rmax, width / 8));
   const int lo = max(0, min(dm_index - 32, n_dm - 64));
@@ -395,22 +399,24 @@ __device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int 
   // are then reduced over the lanes and bin b lands on lane b.
   for (int band = wave; band < 64; band += 4) {
     const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
-    uint32_t acc[64];
-#pragma unroll
-    for (int b = 0; b < 64; ++b) acc[b] = 0;
-    for (int ch = cb + lane; ch < ce; ch += 64)
-      for (int j = 0; j < r; ++j) {
-#pragma unroll
-        for (int b = 0; b < 64; ++b) {
-          const int64_t t = e - (int64_t)(64 - b) * r + 1 + j;
-          if (t >= 0) acc[b] += ft(ch, t);
-        }
-      }
     uint32_t mine = 0;
+    if (!band_sums(band, cb, ce, e, r, mine)) {
+      uint32_t acc[64];
 #pragma unroll
-    for (int b = 0; b < 64; ++b) {
-      const uint32_t tot = wave_sum_u32(acc[b]);
-      if (lane == b) mine = tot;
+      for (int b = 0; b < 64; ++b) acc[b] = 0;
+      for (int ch = cb + lane; ch < ce; ch += 64)
+        for (int j = 0; j < r; ++j) {
+#pragma unroll
+          for (int b = 0; b < 64; ++b) {
+            const int64_t t = e - (int64_t)(64 - b) * r + 1 + j;
+            if (t >= 0) acc[b] += ft(ch, t);
+          }
+        }
+#pragma unroll
+      for (int b = 0; b < 64; ++b) {
+        const uint32_t tot = wave_sum_u32(acc[b]);
+        if (lane == b) mine = tot;
+      }
     }
     const int64_t t0 = e - (int64_t)(64 - lane) * r + 1;
     const int64_t first = max((int64_t)0, t0);
@@ -477,10 +483,25 @@ __device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int 
   }
 }
 
+// Raw rows of one band staged per wave for the tiled band sums.
+static constexpr int kTileRows = 320;
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
   __shared__ double img[2][64 * 64];
   __shared__ double red[3][256];
-  const int tid = threadIdx.x;
+  __shared__ uint4 tiles[4][kTileRows * 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint4 *tile4 = tiles[wave];
+  const uint8_t *tileb = reinterpret_cast<const uint8_t *>(tiles[wave]);
   for (int64_t k = blockIdx.x; k < a.n; k += gridDim.x) {
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
@@ -493,18 +514,71 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
     const CutRow R = a.row[c.seg];
     const uint8_t *fb = a.fb;
     const int nchan = a.nchan;
+    const int D = R.D;
     const double *musig = a.musig;
     const int32_t *dly = R.delays + (int64_t)c.dm_index * nchan;
     auto dm = [&](int tr, int64_t t) { return R.dmt[(int64_t)tr * R.n_out + t]; };
     auto mean = [&](int tr) { return musig[2 * (R.trial0 + tr)]; };
     auto ft = [&](int ch, int64_t t) {
-      const uint8_t *p = fb + ((t + dly[ch]) * R.D) * (int64_t)nchan + ch;
+      const uint8_t *p = fb + ((t + dly[ch]) * D) * (int64_t)nchan + ch;
       uint32_t v = 0;
-      for (int m = 0; m < R.D; ++m) v += p[(int64_t)m * nchan];
+      for (int m = 0; m < D; ++m) v += p[(int64_t)m * nchan];
       return v;
     };
-    cutout_images(c.t_peak + c.width - 1, c.width, c.dm_index, R.n_dm, nchan, a.rmax, dm, mean, ft, img, red,
-                  a.out + (int64_t)k * 2 * 4096);
+    // Tiled band sums: the band's raw rows for a run of bins are read as
+    // 16-byte row segments (a few cache lines per load instead of one per
+    // channel) into the wave's LDS tile, then each lane sums its channel's
+    // shifted rows from there.  Applies when bands are whole 16-byte
+    // segments and the rows of at least one bin plus the band's delay
+    // spread fit the tile.
+    auto band_sums = [&](int band, int cb, int ce, int64_t e, int r, uint32_t &mine) -> bool {
+      if (!a.tiled) return false;
+      int dmin = INT_MAX, dmax = INT_MIN;
+      for (int g0 = cb; g0 < ce; g0 += 64) {
+        const int ch = g0 + lane;
+        dmin = min(dmin, wave_min_i32(ch < ce ? dly[ch] : INT_MAX));
+        dmax = max(dmax, wave_max_i32(ch < ce ? dly[ch] : INT_MIN));
+      }
+      const int64_t spread = (int64_t)dmax - dmin;
+      const int64_t nb = ((int64_t)kTileRows / D - spread) / r;
+      if (nb < 1) return false;
+      const int64_t t0 = e - 64 * (int64_t)r + 1;
+      for (int g0 = cb; g0 < ce; g0 += 64) {
+        const int ch = g0 + lane;
+        const bool valid = ch < ce;
+        const int64_t dc = valid ? dly[ch] : dmin;
+        for (int b0 = 0; b0 < 64; b0 += (int)nb) {
+          const int b1 = (int)min((int64_t)64, b0 + nb);
+          if (t0 + (int64_t)b1 * r - 1 < 0) continue;  // these bins lie before the first sample
+          const int64_t s_lo = max(t0 + (int64_t)b0 * r, (int64_t)0) + dmin;
+          const int64_t s_hi = t0 + (int64_t)b1 * r - 1 + dmax;
+          const int64_t R0 = s_lo * D;
+          const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= kTileRows
+          __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
+          for (int i = lane; i < nrows * 4; i += 64) {
+            const int q = i & 3;
+            if (g0 + 16 * q < ce)
+              tile4[i] = *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> 2)) * (int64_t)nchan + g0 + 16 * q);
+          }
+          __builtin_amdgcn_wave_barrier();
+          for (int b = b0; b < b1; ++b) {
+            const int64_t tb = t0 + (int64_t)b * r;
+            const int jlo = (int)max((int64_t)0, -tb);
+            uint32_t s = 0;
+            if (jlo < r && valid) {
+              const uint8_t *p = tileb + ((tb + jlo + dc) * D - R0) * 64 + (ch - g0);
+              const int nu = (r - jlo) * D;
+              for (int u = 0; u < nu; ++u) s += p[u * 64];
+            }
+            const uint32_t tot = wave_sum_u32(s);
+            if (lane == b) mine += tot;
+          }
+        }
+      }
+      return true;
+    };
+    cutout_images(c.t_peak + c.width - 1, c.width, c.dm_index, R.n_dm, nchan, a.rmax, dm, mean, ft, band_sums, img,
+                  red, a.out + (int64_t)k * 2 * 4096);
   }
 }
 
@@ -525,8 +599,9 @@ __global__ __launch_bounds__(256) void k_cutout_stream(const StreamCut *__restri
     auto ft = [&](int ch, int64_t t) {
       return (uint32_t)C.ring[(int64_t)ch * C.ring_pitch + (t + dly[ch]) % C.R];
     };
-    cutout_images(C.t_peak + C.width - 1, C.width, C.dm_index, C.n_dm, C.nchan, rmax, dm, mean, ft, img, red,
-                  out + k * 2 * 4096);
+    auto no_band_sums = [](int, int, int, int64_t, int, uint32_t &) { return false; };
+    cutout_images(C.t_peak + C.width - 1, C.width, C.dm_index, C.n_dm, C.nchan, rmax, dm, mean, ft, no_band_sums, img,
+                  red, out + k * 2 * 4096);
   }
 }
 
@@ -951,6 +1026,7 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     a.nchan = desc->nchan;
     a.n_seg = desc->n_seg;
     a.rmax = 8;
+    a.tiled = (desc->nchan % 1024 == 0 && reinterpret_cast<uintptr_t>(fb) % 16 == 0) ? 1 : 0;
     a.out = out;
     for (int32_t s = 0; s < desc->n_seg; ++s) {
       RowTables &rt = row_tables(ctx, desc, freqs, s);

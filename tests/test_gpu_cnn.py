@@ -235,6 +235,21 @@ def test_cutouts_multirow(env):
     cutout_case(env, w, desc_rows)
 
 
+@pytest.mark.parametrize("nchan", [1024, 4096])
+def test_cutouts_tiled_bands(env, nchan):
+    """Channel counts whose bands are whole 16-byte row segments: the batch
+    kernel stages each band's raw rows in LDS where the rows of a bin plus
+    the band's delay spread fit (and reads them directly where not: the
+    high-DM trials of the D = 1 row)."""
+    segs = [(0.0, 2.0, 40, 1), (80.0, 4.0, 20, 2), (160.0, 8.0, 12, 4)]
+    w = synth.small(nchan=nchan, nsamp=9000, segments=segs, n_pulses=3, seed_offset=70 + nchan % 7,
+                    widths=[1, 2, 4, 8, 16, 32, 64, 128])
+    # (row, trial, t_peak, width), all inside their rows (n_out 8087, 3587, 1524)
+    extra = [(0, 39, 3000, 128), (0, 0, 0, 64), (0, 20, 5, 9), (1, 19, 3400, 64), (2, 11, 1400, 100),
+             (2, 0, 2, 40), (1, 7, 100, 1)]
+    cutout_case(env, w, extra)
+
+
 def test_cutouts_invalid_candidates_give_zero_images(env):
     gsp, ctx, torch = env
     w = synth.tiny()
