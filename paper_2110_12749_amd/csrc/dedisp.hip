@@ -32,22 +32,70 @@ namespace gsp {
 // ---------------------------------------------------------------------------
 // Staging: time-major uint8 [nsamp][nchan] -> channel-major Y [nchan][pitch]
 // ---------------------------------------------------------------------------
-// Tile = kStageC channels x kStageT outputs.  Read phase: each lane loads a
-// dword (4 channels) of a recorded spectrum and sums the D spectra of one
-// output (nchan % 4 == 0), or single bytes otherwise.  Write phase: a
-// channel row of the tile is written as contiguous dwords.
+// Tile = kStageC channels x kStageT outputs.  Read phase: each lane loads 16
+// bytes (16 channels) of a recorded spectrum (nchan % 16 == 0, 16-byte
+// aligned input), a dword (nchan % 4 == 0) or single bytes otherwise, and
+// sums the D spectra of one output; the 16-byte form keeps four rows of
+// loads in flight per lane.  Write phase: a channel row of the tile is
+// written as contiguous dwords.
 static constexpr int kStageT = 128;  // outputs per tile
 static constexpr int kStageC = 128;  // channels per tile
 static constexpr int kStagePitch = kStageT + 1;  // odd u16 pitch spreads LDS banks
 
-template <typename OutT, bool VEC>
+// MODE: 2 = 16-byte loads, 1 = dword loads, 0 = byte loads.
+template <typename OutT, int MODE>
 __global__ __launch_bounds__(256) void k_stage(const uint8_t *__restrict__ X, int64_t nsamp, int32_t nchan,
                                                int32_t D, int64_t N, OutT *__restrict__ Y, int64_t pitch) {
   __shared__ uint16_t tile[kStageC * kStagePitch];
   const int tid = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * kStageT;
   const int32_t c0 = blockIdx.y * kStageC;
-  if constexpr (VEC) {
+  if constexpr (MODE == 2) {
+    // 8 lanes per 128-channel spectrum, 32 outputs per pass, 4 passes (the
+    // first spectrum of all 4 loaded together); the D spectra of an output
+    // are summed as even/odd bytes in 16-bit halves (255 D <= 65535)
+    const int g = tid & 7;
+    const int c = c0 + 16 * g;
+    const bool cin = c < nchan;
+    uint4 w0[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int64_t j = j0 + (tid >> 3) + 32 * it;
+      w0[it] = (cin && j < N) ? *reinterpret_cast<const uint4 *>(X + (j * D) * (int64_t)nchan + c)
+                              : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int jl = (tid >> 3) + 32 * it;
+      const int64_t j = j0 + jl;
+      uint32_t ev[4], od[4];
+      const uint32_t a[4] = {w0[it].x, w0[it].y, w0[it].z, w0[it].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ev[q] = a[q] & 0x00FF00FFu;
+        od[q] = (a[q] >> 8) & 0x00FF00FFu;
+      }
+      if (cin && j < N) {
+        const uint8_t *p = X + (j * D) * (int64_t)nchan + c;
+        for (int m = 1; m < D; ++m) {
+          const uint4 w = *reinterpret_cast<const uint4 *>(p + (int64_t)m * nchan);
+          const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            ev[q] += wv[q] & 0x00FF00FFu;
+            od[q] += (wv[q] >> 8) & 0x00FF00FFu;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        tile[(16 * g + 4 * q + 0) * kStagePitch + jl] = (uint16_t)(ev[q] & 0xFFFFu);
+        tile[(16 * g + 4 * q + 1) * kStagePitch + jl] = (uint16_t)(od[q] & 0xFFFFu);
+        tile[(16 * g + 4 * q + 2) * kStagePitch + jl] = (uint16_t)(ev[q] >> 16);
+        tile[(16 * g + 4 * q + 3) * kStagePitch + jl] = (uint16_t)(od[q] >> 16);
+      }
+    }
+  } else if constexpr (MODE == 1) {
     const int q = tid & 31;  // channel quad
     const int c = c0 + 4 * q;
     for (int jl = tid >> 5; jl < kStageT; jl += 8) {
@@ -82,22 +130,28 @@ __global__ __launch_bounds__(256) void k_stage(const uint8_t *__restrict__ X, in
     }
   }
   __syncthreads();
-  constexpr int per_dw = 4 / sizeof(OutT);
-  constexpr int row_dw = kStageT / per_dw;
-  for (int idx = tid; idx < kStageC * row_dw; idx += 256) {
-    const int cl = idx / row_dw;
-    const int p = idx % row_dw;
+  // 16 bytes per store: 16 (uint8) or 8 (uint16) outputs of one channel;
+  // rows of Y are 256-element aligned and the tile never crosses the pitch
+  constexpr int per_st = 16 / sizeof(OutT);
+  constexpr int row_st = kStageT / per_st;
+  for (int idx = tid; idx < kStageC * row_st; idx += 256) {
+    const int cl = idx / row_st;
+    const int p = idx % row_st;
     const int c = c0 + cl;
     if (c >= nchan) continue;
-    const int64_t j = j0 + (int64_t)p * per_dw;
+    const int64_t j = j0 + (int64_t)p * per_st;
     if (j >= pitch) continue;
-    const uint16_t *t = tile + cl * kStagePitch + p * per_dw;
-    uint32_t v;
-    if constexpr (sizeof(OutT) == 1)
-      v = (uint32_t)t[0] | ((uint32_t)t[1] << 8) | ((uint32_t)t[2] << 16) | ((uint32_t)t[3] << 24);
-    else
-      v = (uint32_t)t[0] | ((uint32_t)t[1] << 16);
-    *reinterpret_cast<uint32_t *>(Y + (int64_t)c * pitch + j) = v;
+    const uint16_t *t = tile + cl * kStagePitch + p * per_st;
+    uint32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (sizeof(OutT) == 1)
+        v[q] = (uint32_t)t[4 * q] | ((uint32_t)t[4 * q + 1] << 8) | ((uint32_t)t[4 * q + 2] << 16) |
+               ((uint32_t)t[4 * q + 3] << 24);
+      else
+        v[q] = (uint32_t)t[2 * q] | ((uint32_t)t[2 * q + 1] << 16);
+    }
+    *reinterpret_cast<uint4 *>(Y + (int64_t)c * pitch + j) = make_uint4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -227,13 +281,16 @@ void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const 
   dim3 grid((unsigned)((pitch + kStageT - 1) / kStageT), (unsigned)((rt.nchan + kStageC - 1) / kStageC));
   // bytes: the filterbank rows read once + the staged copy written once
   ProfScope prof(ctx, "stage", st, (double)rt.N * rt.D * rt.nchan + (double)pitch * rt.nchan * elem);
-  const bool vec = (rt.nchan % 4) == 0 && (reinterpret_cast<uintptr_t>(fb) % 4) == 0;
+  const uintptr_t fa = reinterpret_cast<uintptr_t>(fb);
+  // 16-byte loads need 16 channels per load and 16-byte rows; their 16-bit
+  // half sums hold D <= 257 spectra of 255
+  const int mode = (rt.nchan % 16 == 0 && fa % 16 == 0 && rt.D <= 257) ? 2 : ((rt.nchan % 4 == 0 && fa % 4 == 0) ? 1 : 0);
   if (rt.D == 1) {
-    auto k = vec ? k_stage<uint8_t, true> : k_stage<uint8_t, false>;
+    auto k = mode == 2 ? k_stage<uint8_t, 2> : (mode == 1 ? k_stage<uint8_t, 1> : k_stage<uint8_t, 0>);
     hipLaunchKernelGGL(k, grid, dim3(256), 0, st, fb, desc->nsamp, rt.nchan, rt.D, rt.N, ctx->staged.as<uint8_t>(),
                        pitch);
   } else {
-    auto k = vec ? k_stage<uint16_t, true> : k_stage<uint16_t, false>;
+    auto k = mode == 2 ? k_stage<uint16_t, 2> : (mode == 1 ? k_stage<uint16_t, 1> : k_stage<uint16_t, 0>);
     hipLaunchKernelGGL(k, grid, dim3(256), 0, st, fb, desc->nsamp, rt.nchan, rt.D, rt.N, ctx->staged.as<uint16_t>(),
                        pitch);
   }
