@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--stream-max-blocks", type=int, default=None)
     ap.add_argument("--triage-weights", default=None, help="stream: attach a trained network (gsp_cnn_save file)")
     ap.add_argument("--triage-threshold", type=float, default=0.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes (otherwise the autotuner picks one per row before the warm-up)")
     ap.add_argument("--shapes", action="store_true",
                     help="time a fixed set of dedispersion tile shapes on every row of the workload (markdown table)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -293,6 +295,12 @@ def main():
     desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
     dmt = torch.empty(desc.total, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
+    shapes = None
+    if not args.no_autotune:  # once per plan, untimed: each row gets its fastest bit-exact shape
+        t = time.perf_counter()
+        shapes = ctx.autotune(fb, w.freqs, desc, out=dmt, stream=stream)
+        torch.cuda.synchronize()
+        log(f"autotune: {shapes} in {time.perf_counter() - t:.1f} s")
 
     net = None if args.no_cnn else gsp.Cnn(ctx, seed=1)
     cut = torch.empty((4096, 2, 64, 64), dtype=torch.int16, device="cuda:0")
@@ -331,6 +339,8 @@ def main():
     ctx.profile_enable(False)
     ms = wall / args.steps * 1e3
     cfg = describe(w, desc)
+    cfg["tile_shapes"] = [list(ctx.row_shape(w.freqs, desc, r)) for r in range(desc.n_seg)]
+    cfg["autotuned"] = shapes is not None
     value = cfg["dm_trial_samples"] / (ms / 1e3)
     rtf = (w.nsamp * w.tsamp) / (ms / 1e3)
     n, tot_ms, adds = prof["dedisperse"]

@@ -246,14 +246,18 @@ class Context:
     def single_pulse_search(self, dmt, desc: DmtDesc, widths, threshold: float, capacity: int = 1 << 16,
                             stream=None) -> np.ndarray:
         w = np.ascontiguousarray(widths, dtype=np.int32)
+        # start from the largest count seen on this context, so that a
+        # repeated search of similar data does not run twice
+        capacity = max(capacity, getattr(self, "_cap_hint", 0))
         while True:
-            out = np.zeros(capacity, CAND_DTYPE)
+            out = np.empty(capacity, CAND_DTYPE)
             n = C.c_int64()
             st = _L.gsp_single_pulse_search(self.h, C.c_void_p(dmt.data_ptr()), C.byref(desc), w.ctypes.data, len(w),
                                             float(threshold), out.ctypes.data, capacity, C.byref(n),
                                             _stream_handle(stream))
             if st == GSP_ECAPACITY:
                 capacity = int(n.value)
+                self._cap_hint = capacity
                 continue
             _check(st, self.h)
             return out[: n.value]
