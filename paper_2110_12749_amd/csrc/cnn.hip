@@ -339,6 +339,11 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t add_dpp_u32(uint32_t v) {
   return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false);
 }
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   x = add_dpp_u32<0x111, 0xf>(x);  // row_shr:1
   x = add_dpp_u32<0x112, 0xf>(x);  // row_shr:2
@@ -587,10 +592,17 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
 // it) and the ring of downsampled samples.  Times before the beam's start
 // count as the window's mean (DM-time) or are left out (frequency-time), as
 // for batch cutouts.
+// Samples per channel row of a wave's tile in the streaming cutouts (pitch
+// padded by 2 so that lanes reading different channels hit different banks).
+static constexpr int kRowS = 128, kRowPitch = kRowS + 2;
+
 __global__ __launch_bounds__(256) void k_cutout_stream(const StreamCut *__restrict__ cuts, int64_t n, int rmax,
                                                        uint16_t *__restrict__ out) {
   __shared__ double img[2][64 * 64];
   __shared__ double red[3][256];
+  __shared__ uint16_t rows[4][64 * kRowPitch];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint16_t *tile = rows[wave];
   for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
     const StreamCut C = cuts[k];
     const int32_t *dly = C.delays + (int64_t)C.dm_index * C.nchan;
@@ -599,8 +611,63 @@ __global__ __launch_bounds__(256) void k_cutout_stream(const StreamCut *__restri
     auto ft = [&](int ch, int64_t t) {
       return (uint32_t)C.ring[(int64_t)ch * C.ring_pitch + (t + dly[ch]) % C.R];
     };
-    auto no_band_sums = [](int, int, int, int64_t, int, uint32_t &) { return false; };
-    cutout_images(C.t_peak + C.width - 1, C.width, C.dm_index, C.n_dm, C.nchan, rmax, dm, mean, ft, no_band_sums, img,
+    // Tiled band sums: for a run of bins, each channel's stretch of its ring
+    // row is copied into the wave's tile by all 64 lanes (contiguous 2-byte
+    // loads, one or two cache lines per load instead of one per channel),
+    // then every lane sums its own channel's bins from LDS.  Bands of at
+    // most 64 channels (one per lane).
+    auto band_sums = [&](int band, int cb, int ce, int64_t e, int r, uint32_t &mine) -> bool {
+      const int nch = ce - cb;
+      if (nch > 64) return false;
+      const int64_t t0 = e - 64 * (int64_t)r + 1;
+      // ring column of time t0 + q for channel cb + lane: (t0 + q + d) mod R;
+      // for a window that starts before the beam (t0 + d < 0) the column is
+      // t0 + q + d itself wherever the time is valid (t0 + q >= 0)
+      const int64_t base_l = t0 + (lane < nch ? dly[cb + lane] : 0);
+      const int64_t p_band = base_l >= 0 ? base_l % C.R : base_l;
+      const int nbp = kRowS / r;  // bins per pass
+      for (int b0 = 0; b0 < 64; b0 += nbp) {
+        const int b1 = min(64, b0 + nbp);
+        const int L = (b1 - b0) * r;  // <= kRowS < R
+        const int64_t ts = t0 + (int64_t)b0 * r;
+        __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
+        for (int cc0 = 0; cc0 < nch; cc0 += 8) {
+          uint16_t v[8][2];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int cc = min(cc0 + u, nch - 1);
+            const uint16_t *rrow = C.ring + (int64_t)(cb + cc) * C.ring_pitch;
+            int64_t p0 = readlane_i64(p_band, cc) + (int64_t)b0 * r;
+            if (p0 >= C.R) p0 -= C.R;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int q = lane + 64 * h;
+              int64_t pos = p0 + q;
+              if (pos >= C.R) pos -= C.R;
+              v[u][h] = (q < L && ts + q >= 0) ? rrow[pos] : (uint16_t)0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              if (cc0 + u < nch && lane + 64 * h < L) tile[(cc0 + u) * kRowPitch + lane + 64 * h] = v[u][h];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const bool has = lane < nch;
+        for (int b = b0; b < b1; ++b) {
+          uint32_t s = 0;
+          if (has) {
+            const uint16_t *p = tile + lane * kRowPitch + (b - b0) * r;
+            for (int j = 0; j < r; ++j) s += p[j];
+          }
+          const uint32_t tot = wave_sum_u32(s);
+          if (lane == b) mine = tot;
+        }
+      }
+      return true;
+    };
+    cutout_images(C.t_peak + C.width - 1, C.width, C.dm_index, C.n_dm, C.nchan, rmax, dm, mean, ft, band_sums, img,
                   red, out + k * 2 * 4096);
   }
 }

@@ -243,30 +243,77 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
       max_e = std::max<int64_t>(max_e, delay(tl * MT + MT - 1, c) - b);
     }
   const int K = shape.groups;
-  // a multiple of 8 dwords: whole 16-sample staging units, 16-byte aligned rows
-  rt.row_dwords = (int32_t)((((max_e >> 1) + 64 * K + 1) + 7) & ~7);
-  // channels per staging pass: as many as fit the LDS budget (two copies of
-  // row_dwords dwords + MT offsets + 2 bases per channel), as the staging
-  // registers allow, and at most the requested chunk
-  const int threads = 64 * shape.waves;
-  const int64_t per_chan = 2 * (int64_t)rt.row_dwords * 4 + (int64_t)MT * 4 + 8;
-  int64_t chunk64 = std::min<int64_t>(shape.chunk, std::max<int64_t>(1, kLdsBudget / per_chan));
-  chunk64 = std::min<int64_t>(chunk64, (int64_t)kUnitMax * threads / (rt.row_dwords / 8));
-  chunk64 = std::min<int64_t>(chunk64, threads / MT);
-  if (chunk64 < 1 || chunk64 * per_chan > kLdsMax)
-    fail(GSP_EINVAL, "dedispersion tile does not fit in LDS (delay spread too wide)");
-  const int chunk = (int)chunk64;
-  rt.shape.chunk = chunk;
-  rt.lds_bytes = (int64_t)chunk * per_chan;
-  std::vector<uint32_t> addr((size_t)nchan * n_dm_pad);
+  // staged window per channel: the widest delay spread of a DM tile at that
+  // channel plus the tile's samples, in dwords, a multiple of 8 (whole
+  // 16-sample staging units, 16-byte aligned rows)
+  std::vector<int32_t> row_dw_c(nchan);
+  int32_t widest = 0;
   for (int c = 0; c < nchan; ++c) {
-    const int cl = c % chunk;
-    for (int i = 0; i < n_dm_pad; ++i) {
-      const int tl = i / MT;
-      const int32_t e = delay(i, c) - base[(size_t)tl * nchan + c];
-      addr[(size_t)c * n_dm_pad + i] = (uint32_t)((cl * 2 + (e & 1)) * rt.row_dwords + (e >> 1));
+    int64_t e = 0;
+    for (int tl = 0; tl < n_tiles; ++tl) e = std::max<int64_t>(e, delay(tl * MT + MT - 1, c) - base[(size_t)tl * nchan + c]);
+    row_dw_c[c] = (int32_t)((((e >> 1) + 64 * K + 1) + 7) & ~7);
+    widest = std::max(widest, row_dw_c[c]);
+  }
+  rt.row_dwords = widest;
+  // staging passes over consecutive channels (neighbouring frequencies,
+  // similar spreads): each as long as its staged copies fit the LDS budget
+  // left after the offsets and bases of the longest allowed pass, the
+  // staging registers (kUnitMax units per thread) hold it, and at most the
+  // requested number of channels
+  const int threads = 64 * shape.waves;
+  const int64_t kmax = std::min<int64_t>({(int64_t)shape.chunk, (int64_t)kOffMax * threads / MT, (int64_t)threads});
+  if (kmax < 1) fail(GSP_EINVAL, "unsupported dedispersion shape");
+  const int64_t side = kmax * ((int64_t)MT * 4 + 8);  // offsets + two bases per channel, bytes
+  const int64_t data_budget = kLdsBudget - side;
+  std::vector<int32_t> passes;  // start, row dwords pairs
+  int64_t data_dw = 0;
+  int max_chunk = 0;
+  for (int c = 0; c < nchan;) {
+    int k = 0;
+    int32_t rd = 0;
+    while (c + k < nchan) {
+      const int32_t rd2 = std::max(rd, row_dw_c[c + k]);
+      const int64_t k2 = k + 1;
+      const bool fits = k2 <= kmax && 2 * k2 * rd2 * 4 <= data_budget && k2 * (rd2 / 8) <= (int64_t)kUnitMax * threads;
+      if (!fits && k > 0) break;
+      if (!fits) {  // one channel alone: still allowed up to the hardware LDS if the registers hold it
+        if (rd2 / 8 > (int64_t)kUnitMax * threads || 2 * (int64_t)rd2 * 4 + side > kLdsMax)
+          fail(GSP_EINVAL, "dedispersion tile does not fit in LDS (delay spread too wide)");
+      }
+      rd = rd2;
+      k = (int)k2;
+      if (!fits) break;
+    }
+    passes.push_back(c);
+    passes.push_back(rd);
+    data_dw = std::max<int64_t>(data_dw, 2 * (int64_t)k * rd);
+    max_chunk = std::max(max_chunk, k);
+    c += k;
+  }
+  passes.push_back(nchan);
+  passes.push_back(0);
+  rt.n_passes = (int32_t)(passes.size() / 2 - 1);
+  rt.max_chunk = max_chunk;
+  rt.data_dw = (int32_t)data_dw;
+  rt.shape.chunk = max_chunk;
+  rt.lds_bytes = data_dw * 4 + (int64_t)max_chunk * ((int64_t)MT * 4 + 8);
+  if (rt.lds_bytes > kLdsMax) fail(GSP_EINVAL, "dedispersion tile does not fit in LDS (delay spread too wide)");
+  std::vector<uint32_t> addr((size_t)nchan * n_dm_pad);
+  for (size_t q = 0; q + 2 < passes.size(); q += 2) {
+    const int cs = passes[q], ce = passes[q + 2];
+    const int32_t rd = passes[q + 1];
+    for (int c = cs; c < ce; ++c) {
+      const int cl = c - cs;
+      for (int i = 0; i < n_dm_pad; ++i) {
+        const int tl = i / MT;
+        const int32_t e = delay(i, c) - base[(size_t)tl * nchan + c];
+        addr[(size_t)c * n_dm_pad + i] = (uint32_t)((cl * 2 + (e & 1)) * rd + (e >> 1));
+      }
     }
   }
+  rt.passes.device = ctx->device;
+  rt.passes.reserve(passes.size() * 4);
+  check_hip(hipMemcpy(rt.passes.ptr, passes.data(), passes.size() * 4, hipMemcpyHostToDevice), "copy staging passes");
   rt.addr.reserve(addr.size() * 4);
   rt.dmin.reserve(base.size() * 4);
   check_hip(hipMemcpy(rt.addr.ptr, addr.data(), addr.size() * 4, hipMemcpyHostToDevice), "copy LDS offsets");
@@ -332,9 +379,11 @@ void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStrea
   a.n_dm_tiles = (rt.n_dm + MT - 1) / MT;
   a.n_dm_pad = a.n_dm_tiles * MT;
   a.nchan = rt.nchan;
-  a.chunk = sh.chunk;
+  a.chunks = rt.passes.as<int32_t>();
+  a.n_chunks = rt.n_passes;
+  a.max_chunk = rt.max_chunk;
+  a.data_dw = rt.data_dw;
   a.flush = flush_interval(rt.D);
-  a.row_dw = rt.row_dwords;
   const int64_t T = sh.samples_per_block();
   a.n_t_tiles = (int32_t)((rt.n_out + T - 1) / T);
   if ((int64_t)a.n_dm_tiles * a.n_t_tiles >= (1LL << 31)) fail(GSP_EOVERFLOW, "too many dedispersion tiles");

@@ -18,9 +18,14 @@ struct DedispArgs {
   int64_t ring;             // staged samples per channel in a ring (0: linear copy)
   int64_t phys0;            // position of sample t_origin in the staged row (multiple of 4)
   int32_t n_dm, n_dm_pad, nchan;
-  int32_t chunk;            // channels per staging pass
+  // staging passes: pass k covers channels [chunks[2k], chunks[2k+2]) with
+  // chunks[2k+1] dwords per staged copy of a channel (a multiple of 8);
+  // chunks[2 n_chunks] = nchan
+  const int32_t *chunks;
+  int32_t n_chunks;
+  int32_t max_chunk;        // most channels in one pass
+  int32_t data_dw;          // LDS dwords of the largest pass's staged copies
   int32_t flush;            // channels between flushes of the 16-bit lanes
-  int32_t row_dw;           // dwords per staged copy of a channel
   int32_t n_dm_tiles, n_t_tiles;
 };
 
@@ -33,8 +38,11 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 }
 
 // Staging unit: 16 consecutive samples of one channel, i.e. 8 dwords of each
-// LDS copy.  Each thread stages at most kUnitMax units per chunk.
+// LDS copy.  Each thread stages at most kUnitMax units and kOffMax trial
+// offsets per pass (a second offset per thread measured 4 % slower on the
+// realistic plan, for passes no longer than one offset per thread allows).
 static constexpr int kUnitMax = 2;
+static constexpr int kOffMax = 1;
 
 template <typename SrcT>
 struct Unit {
@@ -58,25 +66,38 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
   const int64_t t0 = a.t_origin + t_rel;
   const int MT = TPW * nwaves;
   const int i_tile = dm_tile * MT;
-  const int row_dw = a.row_dw;  // multiple of 8
-  const int U = row_dw >> 3;    // staging units per channel
-  const int chunk = a.chunk;
-  const int n_chunks = (a.nchan + chunk - 1) / chunk;
-  // LDS: samples [chunk][2][row_dw] | offsets [chunk][MT] | staging bases [2][chunk]
+  const int n_chunks = a.n_chunks;
+  const int maxc = a.max_chunk;
+  // LDS: samples [pass channels][2][row dwords] | offsets [max_chunk][MT] | staging bases [2][max_chunk]
   uint32_t *data = lds;
-  uint32_t *offs = lds + 2 * chunk * row_dw;
-  int32_t *bases = reinterpret_cast<int32_t *>(offs + chunk * MT);
+  uint32_t *offs = lds + a.data_dw;
+  int32_t *bases = reinterpret_cast<int32_t *>(offs + maxc * MT);
+  // the pass table is read 64 passes at a time into one register per lane
+  // (lane l: pass w0 + l) and taken with readlane, so no scalar load (whose
+  // wait would also drain the LDS queue) sits in the pass loop
+  int w0 = 0;
+  int32_t win_cs = 0, win_rd = 0;
+  auto fetch_window = [&](int from) {
+    w0 = from;
+    const int j = from + lane;
+    win_cs = j <= n_chunks ? a.chunks[2 * j] : a.nchan;
+    win_rd = j < n_chunks ? a.chunks[2 * j + 1] : 8;
+  };
+  auto ch_begin = [&](int j) { return __builtin_amdgcn_readlane(win_cs, j - w0); };
+  auto row_dw_of = [&](int j) { return __builtin_amdgcn_readlane(win_rd, j - w0); };
+  fetch_window(0);
 
   const SrcT *Y = static_cast<const SrcT *>(a.Y);
   const int32_t *base_row = a.base + (int64_t)dm_tile * a.nchan;
 
   // ---- staging helpers ----
   Unit<SrcT> pu[kUnitMax];
-  uint32_t poff = 0;
-  auto prefetch = [&](int j) {  // global -> registers for chunk j (bases of j already in LDS)
-    const int cs = j * chunk, ce = min(cs + chunk, a.nchan);
+  uint32_t poff[kOffMax] = {0};
+  auto prefetch = [&](int j) {  // global -> registers for pass j (bases of j already in LDS)
+    const int cs = ch_begin(j), ce = ch_begin(j + 1);
+    const int U = row_dw_of(j) >> 3;  // staging units per channel
     const int nu = (ce - cs) * U;
-    const int32_t *bj = bases + (j & 1) * chunk;
+    const int32_t *bj = bases + (j & 1) * maxc;
     // all addresses first, then all loads, so every load is issued back to back
     const SrcT *rows[kUnitMax];
 #pragma unroll
@@ -96,10 +117,16 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       for (int m = 0; m < Unit<SrcT>::W; ++m) pu[i].w[m] = w[m];
       pu[i].tail = rows[i][16];
     }
-    if (tid < (ce - cs) * MT) poff = a.addr[(int64_t)(cs + tid / MT) * a.n_dm_pad + i_tile + tid % MT];
+#pragma unroll
+    for (int i = 0; i < kOffMax; ++i) {
+      const int q = tid + i * nthreads;
+      if (q < (ce - cs) * MT) poff[i] = a.addr[(int64_t)(cs + q / MT) * a.n_dm_pad + i_tile + q % MT];
+    }
   };
-  auto store = [&](int j) {  // registers -> LDS for chunk j
-    const int cs = j * chunk, ce = min(cs + chunk, a.nchan);
+  auto store = [&](int j) {  // registers -> LDS for pass j
+    const int cs = ch_begin(j), ce = ch_begin(j + 1);
+    const int row_dw = row_dw_of(j);
+    const int U = row_dw >> 3;
     const int nu = (ce - cs) * U;
 #pragma unroll
     for (int i = 0; i < kUnitMax; ++i) {
@@ -138,7 +165,11 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
         d1[1] = make_uint4(c1[4], c1[5], c1[6], c1[7]);
       }
     }
-    if (tid < (ce - cs) * MT) offs[tid] = poff;
+#pragma unroll
+    for (int i = 0; i < kOffMax; ++i) {
+      const int q = tid + i * nthreads;
+      if (q < (ce - cs) * MT) offs[q] = poff[i];
+    }
   };
 
   // ---- accumulators ----
@@ -189,27 +220,29 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
     }
   };
 
-  // ---- prologue: bases of chunks 0 (LDS) and 1 (register), samples of chunk 0 ----
-  if (tid < chunk) bases[tid] = tid < a.nchan ? base_row[tid] : 0;
-  int32_t pbase = (tid < chunk && chunk + tid < a.nchan) ? base_row[chunk + tid] : 0;
+  // ---- prologue: bases of passes 0 (LDS) and 1 (register), samples of pass 0 ----
+  // (a pass has at most max_chunk <= threads channels: one base per thread)
+  if (tid < ch_begin(1) - ch_begin(0)) bases[tid] = base_row[ch_begin(0) + tid];
+  int32_t pbase = (n_chunks > 1 && tid < ch_begin(2) - ch_begin(1)) ? base_row[ch_begin(1) + tid] : 0;
   __syncthreads();
   prefetch(0);
 
   for (int kc = 0; kc < n_chunks; ++kc) {
-    const int cs = kc * chunk, ce = min(cs + chunk, a.nchan);
-    __syncthreads();  // every wave is done with chunk kc-1
+    if (kc + 3 > w0 + 63) fetch_window(kc);  // passes kc .. kc + 3 are read below
+    const int cs = ch_begin(kc), ce = ch_begin(kc + 1);
+    __syncthreads();  // every wave is done with pass kc-1
     store(kc);
-    if (tid < chunk) bases[((kc + 1) & 1) * chunk + tid] = pbase;
+    if (tid < maxc) bases[((kc + 1) & 1) * maxc + tid] = pbase;
     __syncthreads();
-    // in flight during the accumulation below: samples of chunk kc+1, bases of kc+2
-    if (kc + 2 < n_chunks && tid < chunk)
-      pbase = (kc + 2) * chunk + tid < a.nchan ? base_row[(kc + 2) * chunk + tid] : 0;
+    // in flight during the accumulation below: samples of pass kc+1, bases of kc+2
+    if (kc + 2 < n_chunks)
+      pbase = tid < ch_begin(kc + 3) - ch_begin(kc + 2) ? base_row[ch_begin(kc + 2) + tid] : 0;
     if (kc + 1 < n_chunks) prefetch(kc + 1);
 
-    // ---- accumulate chunk kc: per channel TPW trials x K dwords per lane ----
+    // ---- accumulate pass kc: per channel TPW trials x K dwords per lane ----
     // two register sets: while one channel is added, the next one's samples
     // and the one after's offsets are in flight (LDS returns in order).  The
-    // loads are unconditional (channel index clamped to the chunk) so that no
+    // loads are unconditional (channel index clamped to the pass) so that no
     // branch forces a full wait before the adds.
     const uint32_t *orow = offs + wave * TPW;
     const int last = ce - 1 - cs;

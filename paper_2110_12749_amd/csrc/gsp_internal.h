@@ -54,7 +54,9 @@ struct RowTables {
   DedispShape shape;
   int32_t req_chunk = 0;     // chunk requested by the shape (before LDS limits)
   int64_t lds_bytes = 0;     // dynamic LDS per block
-  int32_t row_dwords = 0;    // LDS dwords per staged copy of a channel
+  int32_t row_dwords = 0;    // LDS dwords per staged copy of the widest channel
+  DevBuf passes;             // int32 pairs (first channel, dwords per staged copy) per staging pass + end
+  int32_t n_passes = 0, max_chunk = 0, data_dw = 0;
   DevBuf addr;               // uint32 [n_dm_pad][nchan]: LDS dword offset per (trial, channel)
   DevBuf dmin;               // int32 [n_tiles][nchan]: aligned first delay per DM tile
   DevBuf delays_dev;         // int32 [n_dm][nchan] (cutouts)

@@ -513,9 +513,11 @@ int64_t step_once(gsp_stream *s) {
       A.n_dm_tiles = (R.n_dm + MT - 1) / MT;
       A.n_dm_pad = A.n_dm_tiles * MT;
       A.nchan = b.nchan;
-      A.chunk = rt.shape.chunk;
+      A.chunks = rt.passes.as<int32_t>();
+      A.n_chunks = rt.n_passes;
+      A.max_chunk = rt.max_chunk;
+      A.data_dw = rt.data_dw;
       A.flush = std::max(1, std::min(65535 / (255 * R.D), 256));
-      A.row_dw = rt.row_dwords;
       const int64_t T = rt.shape.samples_per_block();
       A.n_t_tiles = (int32_t)((e - origin + T - 1) / T);
       D.item0 = td.n_items;
