@@ -560,10 +560,21 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
           const int64_t R0 = s_lo * D;
           const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= kTileRows
           __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
-          for (int i = lane; i < nrows * 4; i += 64) {
-            const int q = i & 3;
-            if (g0 + 16 * q < ce)
-              tile4[i] = *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> 2)) * (int64_t)nchan + g0 + 16 * q);
+          // 8 loads in flight per lane before their LDS stores
+          for (int i0 = lane; i0 < nrows * 4; i0 += 64 * 8) {
+            uint4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = min(i0 + 64 * u, nrows * 4 - 1);
+              const int q = i & 3;
+              v[u] = g0 + 16 * q < ce ? *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> 2)) * (int64_t)nchan + g0 + 16 * q)
+                                      : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 + 64 * u;
+              if (i < nrows * 4) tile4[i] = v[u];
+            }
           }
           __builtin_amdgcn_wave_barrier();
           for (int b = b0; b < b1; ++b) {

@@ -136,17 +136,20 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
         const int p = u - cl * U;
         uint32_t c0[8], c1[8];
         if constexpr (sizeof(SrcT) == 1) {
-          // samples y0..y15 in 4 dwords, y16 in tail
+          // samples y0..y15 in 4 dwords, y16 in tail; each 16-bit pair is one
+          // byte permute (selector byte k < 4: byte k of the second operand,
+          // 4..7: byte k-4 of the first, 0x0c: zero)
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
             const uint32_t w = pu[i].w[m >> 1];
             const uint32_t wn = (m >> 1) + 1 < 4 ? pu[i].w[(m >> 1) + 1] : pu[i].tail;
-            const int b = (m & 1) * 2;  // byte of sample 2m within w
-            const uint32_t ya = (w >> (8 * b)) & 0xFFu;
-            const uint32_t yb = (w >> (8 * b + 8)) & 0xFFu;
-            const uint32_t yc = b == 2 ? (wn & 0xFFu) : ((w >> (8 * b + 16)) & 0xFFu);
-            c0[m] = ya | (yb << 16);
-            c1[m] = yb | (yc << 16);
+            if (m & 1) {
+              c0[m] = __builtin_amdgcn_perm(0u, w, 0x0C030C02u);  // (y[2m], y[2m+1]) = bytes 2, 3
+              c1[m] = __builtin_amdgcn_perm(wn, w, 0x0C040C03u);  // byte 3 of w, byte 0 of wn
+            } else {
+              c0[m] = __builtin_amdgcn_perm(0u, w, 0x0C010C00u);  // bytes 0, 1
+              c1[m] = __builtin_amdgcn_perm(0u, w, 0x0C020C01u);  // bytes 1, 2
+            }
           }
         } else {
 #pragma unroll
