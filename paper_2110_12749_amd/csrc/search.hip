@@ -165,6 +165,22 @@ __device__ __forceinline__ int64_t wave_scan_i64(int64_t x) {
   return x;
 }
 
+// Inclusive scan of an int32 over the 64 lanes (same DPP pattern as the
+// int64 scan below), for partial sums known to fit.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t add_dpp_i32(int32_t v) {
+  return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ int32_t wave_scan_i32(int32_t x) {
+  x = add_dpp_i32<0x111, 0xf>(x);
+  x = add_dpp_i32<0x112, 0xf>(x);
+  x = add_dpp_i32<0x114, 0xf>(x);
+  x = add_dpp_i32<0x118, 0xf>(x);
+  x = add_dpp_i32<0x142, 0xa>(x);
+  x = add_dpp_i32<0x143, 0xc>(x);
+  return x;
+}
+
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
@@ -210,6 +226,9 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
     const int64_t seg = local - (int64_t)trial * J.tiles;
     const int g = J.trial0 + trial;
     const double mu = a.musig[2 * g], sigma = a.musig[2 * g + 1];
+    // an integer near the mean (any value is exact; near the mean keeps the
+    // centred samples small)
+    const int64_t cmean = (int64_t)fmin(fmax(rint(mu), -2147483648.0), 2147483647.0);
     if (!(sigma > 0.0)) continue;  // uniform over the wave
     const int32_t *x = J.x + (int64_t)trial * J.pitch + J.e_begin;  // relative positions
     const int64_t look = J.look;
@@ -278,7 +297,14 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
         const int64_t e = eb + 64 * it + lane;
-        P[it] = carry + wave_scan_i64(e < s1 ? (int64_t)v[it] : 0);
+        // samples about the trial's integer mean c: when every |x - c| of the
+        // step is below 2^25 their 64-lane partial sums fit an int32 scan
+        // (positions past the segment count as c, i.e. add nothing)
+        const int64_t y = e < s1 ? (int64_t)v[it] - cmean : 0;
+        if (__ballot(y <= -(int64_t)(1 << 25) || y >= (int64_t)(1 << 25)) == 0ull)
+          P[it] = carry + (int64_t)wave_scan_i32((int32_t)y) + cmean * (int64_t)(lane + 1);
+        else
+          P[it] = carry + wave_scan_i64(y) + cmean * (int64_t)(lane + 1);
         carry = lane63(P[it]);
         W.ring[(r0 + 64 * it + lane) & (RING - 1)] = P[it];
       }
