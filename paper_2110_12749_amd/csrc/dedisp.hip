@@ -169,7 +169,7 @@ DedispShape default_shape(int32_t D) {
   s.tpw = 4;
   s.waves = 8;
   s.groups = 4;
-  s.chunk = 16;
+  s.chunk = 32;
   (void)D;
   return s;
 }
@@ -212,7 +212,7 @@ int64_t staged_pitch(const RowTables &rt) {
 }
 
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
-                      const DedispShape &shape, RowTables &rt) {
+                      const DedispShape &shape, RowTables &rt, int units_per_thread) {
   const gsp_segment &g = desc->seg[s];
   rt.n_dm = g.n_dm;
   rt.D = g.downsamp;
@@ -258,9 +258,10 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
   // staging passes over consecutive channels (neighbouring frequencies,
   // similar spreads): each as long as its staged copies fit the LDS budget
   // left after the offsets and bases of the longest allowed pass, the
-  // staging registers (kUnitMax units per thread) hold it, and at most the
+  // staging registers (`units` per thread) hold it, and at most the
   // requested number of channels
   const int threads = 64 * shape.waves;
+  const int units = units_per_thread > 0 ? units_per_thread : unit_max_for_d(g.downsamp);
   const int64_t kmax = std::min<int64_t>({(int64_t)shape.chunk, (int64_t)kOffMax * threads / MT, (int64_t)threads});
   if (kmax < 1) fail(GSP_EINVAL, "unsupported dedispersion shape");
   const int64_t side = kmax * ((int64_t)MT * 4 + 8);  // offsets + two bases per channel, bytes
@@ -274,10 +275,10 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
     while (c + k < nchan) {
       const int32_t rd2 = std::max(rd, row_dw_c[c + k]);
       const int64_t k2 = k + 1;
-      const bool fits = k2 <= kmax && 2 * k2 * rd2 * 4 <= data_budget && k2 * (rd2 / 8) <= (int64_t)kUnitMax * threads;
+      const bool fits = k2 <= kmax && 2 * k2 * rd2 * 4 <= data_budget && k2 * (rd2 / 8) <= (int64_t)units * threads;
       if (!fits && k > 0) break;
       if (!fits) {  // one channel alone: still allowed up to the hardware LDS if the registers hold it
-        if (rd2 / 8 > (int64_t)kUnitMax * threads || 2 * (int64_t)rd2 * 4 + side > kLdsMax)
+        if (rd2 / 8 > (int64_t)units * threads || 2 * (int64_t)rd2 * 4 + side > kLdsMax)
           fail(GSP_EINVAL, "dedispersion tile does not fit in LDS (delay spread too wide)");
       }
       rd = rd2;

@@ -38,11 +38,14 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 }
 
 // Staging unit: 16 consecutive samples of one channel, i.e. 8 dwords of each
-// LDS copy.  Each thread stages at most kUnitMax units and kOffMax trial
-// offsets per pass (a second offset per thread measured 4 % slower on the
-// realistic plan, for passes no longer than one offset per thread allows).
-static constexpr int kUnitMax = 2;
-static constexpr int kOffMax = 1;
+// LDS copy.  Per pass each thread stages at most unit_max units (uint8
+// sources: 3; uint16 sources, 9 registers a unit: 2, which keeps 4 waves per
+// SIMD) and kOffMax trial offsets (two, loaded and stored as one 8-byte
+// pair).  Longer passes mean fewer workgroup barriers per channel.
+template <typename SrcT>
+constexpr int unit_max() { return sizeof(SrcT) == 1 ? 3 : 2; }
+constexpr int unit_max_for_d(int D) { return D == 1 ? 3 : 2; }
+static constexpr int kOffMax = 2;
 
 template <typename SrcT>
 struct Unit {
@@ -91,17 +94,17 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
   const int32_t *base_row = a.base + (int64_t)dm_tile * a.nchan;
 
   // ---- staging helpers ----
-  Unit<SrcT> pu[kUnitMax];
-  uint32_t poff[kOffMax] = {0};
+  Unit<SrcT> pu[unit_max<SrcT>()];
+  uint2 poff = make_uint2(0, 0);
   auto prefetch = [&](int j) {  // global -> registers for pass j (bases of j already in LDS)
     const int cs = ch_begin(j), ce = ch_begin(j + 1);
     const int U = row_dw_of(j) >> 3;  // staging units per channel
     const int nu = (ce - cs) * U;
     const int32_t *bj = bases + (j & 1) * maxc;
     // all addresses first, then all loads, so every load is issued back to back
-    const SrcT *rows[kUnitMax];
+    const SrcT *rows[unit_max<SrcT>()];
 #pragma unroll
-    for (int i = 0; i < kUnitMax; ++i) {
+    for (int i = 0; i < unit_max<SrcT>(); ++i) {
       const int u = min(tid + i * nthreads, nu - 1);  // clamped: loads stay in bounds
       const int cl = u / U;
       const int p = u - cl * U;
@@ -111,16 +114,17 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       rows[i] = Y + (int64_t)(cs + cl) * a.pitch + e0;
     }
 #pragma unroll
-    for (int i = 0; i < kUnitMax; ++i) {
+    for (int i = 0; i < unit_max<SrcT>(); ++i) {
       const uint32_t *w = reinterpret_cast<const uint32_t *>(rows[i]);
 #pragma unroll
       for (int m = 0; m < Unit<SrcT>::W; ++m) pu[i].w[m] = w[m];
       pu[i].tail = rows[i][16];
     }
-#pragma unroll
-    for (int i = 0; i < kOffMax; ++i) {
-      const int q = tid + i * nthreads;
-      if (q < (ce - cs) * MT) poff[i] = a.addr[(int64_t)(cs + q / MT) * a.n_dm_pad + i_tile + q % MT];
+    {
+      // offsets 2 tid and 2 tid + 1 of the pass (same channel: MT is even)
+      const int q = 2 * tid;
+      if (q < (ce - cs) * MT)
+        poff = *reinterpret_cast<const uint2 *>(a.addr + (int64_t)(cs + q / MT) * a.n_dm_pad + i_tile + q % MT);
     }
   };
   auto store = [&](int j) {  // registers -> LDS for pass j
@@ -129,7 +133,7 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
     const int U = row_dw >> 3;
     const int nu = (ce - cs) * U;
 #pragma unroll
-    for (int i = 0; i < kUnitMax; ++i) {
+    for (int i = 0; i < unit_max<SrcT>(); ++i) {
       const int u = tid + i * nthreads;
       if (u < nu) {
         const int cl = u / U;
@@ -168,10 +172,9 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
         d1[1] = make_uint4(c1[4], c1[5], c1[6], c1[7]);
       }
     }
-#pragma unroll
-    for (int i = 0; i < kOffMax; ++i) {
-      const int q = tid + i * nthreads;
-      if (q < (ce - cs) * MT) offs[q] = poff[i];
+    {
+      const int q = 2 * tid;
+      if (q < (ce - cs) * MT) *reinterpret_cast<uint2 *>(offs + q) = poff;
     }
   };
 

@@ -175,8 +175,10 @@ DedispShape default_shape(int32_t D);
 bool shape_supported(const DedispShape &s);
 std::string row_signature(const gsp_dmt_desc *desc, int32_t s);
 DedispShape shape_for_row(gsp_ctx *ctx, const gsp_dmt_desc *desc, int32_t s);
+// units_per_thread: staging units each thread holds (the kernel's
+// unit_max for its source type); 0 = the batch kernel's for the row's D
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
-                      const DedispShape &shape, RowTables &rt);
+                      const DedispShape &shape, RowTables &rt, int units_per_thread = 0);
 void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st);
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 int64_t staged_pitch(const RowTables &rt);

@@ -334,7 +334,7 @@ void plan_beam(gsp_stream *s, Beam &b) {
   sh.groups = kStreamGroups;
   sh.tpw = kStreamTpw;
   sh.waves = kStreamWaves;
-  sh.chunk = 16;
+  sh.chunk = 32;
   for (int32_t r = 0; r < d.n_seg; ++r) {
     if (s->B % (4 * d.seg[r].downsamp))
       fail(GSP_EINVAL, "block length must be a multiple of 4 x every downsampling factor");
@@ -349,7 +349,7 @@ void plan_beam(gsp_stream *s, Beam &b) {
     row->tables.addr.device = s->ctx->device;
     row->tables.dmin.device = s->ctx->device;
     // the staged rows are uint16 for every D in a stream (one kernel instance)
-    build_row_tables(s->ctx, &d, b.freqs.data(), r, sh, row->tables);
+    build_row_tables(s->ctx, &d, b.freqs.data(), r, sh, row->tables, unit_max<uint16_t>());  // rings are uint16
     b.rows.push_back(std::move(row));
   }
 }
