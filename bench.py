@@ -193,8 +193,8 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
                 "ms_per_block": rep["triage_s"] / max(1, rep["blocks"]) * 1e3}}
 
 
-SWEEP_SHAPES = [(4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 16), (4, 8, 4, 16), (2, 8, 8, 16), (2, 8, 4, 32),
-                (8, 4, 8, 16), (4, 4, 16, 16)]
+SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8, 4, 32), (2, 8, 8, 32),
+                (8, 4, 8, 32)]
 
 
 def shape_sweep(w):
