@@ -248,8 +248,12 @@ int gsp_stream_set_graph(gsp_stream *s, int enable);
 
 /* Launch shape of the dedispersion kernel for one plan row: each workgroup
  * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials
- * over 128*`groups` output samples; `chunk` channels are staged into LDS per
- * pass (the library lowers it to fit LDS and its staging registers). */
+ * over 128*`groups` output samples; at most `chunk` channels are staged into
+ * LDS per pass.  Passes run over consecutive channels and each is as long as
+ * the LDS budget, the staging registers and the trial offsets a thread loads
+ * allow for the staged windows of its channels (a channel's window covers
+ * the delay spread of a tile of trials at that channel), up to `chunk`.
+ * gsp_row_shape reports the longest pass in `chunk`. */
 typedef struct gsp_shape {
   int32_t groups; /* 2, 4 or 8 */
   int32_t tpw;    /* 4 or 8 */
