@@ -235,7 +235,7 @@ def test_cutouts_multirow(env):
     cutout_case(env, w, desc_rows)
 
 
-@pytest.mark.parametrize("nchan", [1024, 4096])
+@pytest.mark.parametrize("nchan", [1024, 4096, 8192])
 def test_cutouts_tiled_bands(env, nchan):
     """Channel counts whose bands are whole 16-byte row segments: the batch
     kernel stages each band's raw rows in LDS where the rows of a bin plus

@@ -86,6 +86,7 @@ def test_tiny_full_parity_and_pulse(env):
     (200, 12345, [(0.0, 0.5, 40, 1), (20.0, 1.0, 30, 4), (50.0, 4.0, 17, 8)]),
     (300, 4099, [(0.0, 0.25, 5, 1)]),                    # more channels than one flush of 256
     (1, 3000, [(0.0, 1.0, 3, 1)]),                       # one channel
+    (8192, 4000, [(0.0, 0.5, 40, 1), (20.0, 1.0, 24, 2)]),  # two 64-lane groups per cutout band, long passes
 ])
 def test_small_plans_parity(env, nchan, nsamp, segs):
     w = synth.small(nchan=nchan, nsamp=nsamp, segments=segs, n_pulses=2)
