@@ -69,13 +69,23 @@ struct GemmArgs {
   int32_t im_C, im_H;
 };
 
-static constexpr int kTM = 64, kTN = 64, kTK = 16;
+static constexpr int kTM = 64, kTN = 64, kTK = 32;
+static constexpr int kTP = kTK + 8;  // padded LDS row: 80 bytes, 16-byte aligned
 
 static unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 64); }
 
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Workgroup tile 64 x 64, k step 32.  Each thread stages 8 consecutive k of
+// one A row and of one B column: one 16-byte load where the operand is
+// contiguous and aligned along k (plain A with unit k stride, implicit
+// im2col over channel-contiguous activations, B with unit k stride), 8
+// element loads otherwise.  B is kept transposed in LDS ([n][k]) so that
+// both MFMA operands are 8-byte LDS reads.  The next k step's operands are
+// loaded into registers while the current one is multiplied.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ uint16_t As[kTM][kTK + 2];
-  __shared__ uint16_t Bs[kTK][kTN + 2];
+  __shared__ __align__(16) uint16_t As[kTM][kTP];
+  __shared__ __align__(16) uint16_t Bt[kTN][kTP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -85,62 +95,89 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const bool split = gridDim.z > 1;
   const int k_begin = split ? (int)blockIdx.z * g.k_chunk : 0;
   const int k_end = split ? min(g.K, k_begin + g.k_chunk) : g.K;
+  // this thread's A row / B column and k offset inside a step
+  const int srow = tid >> 2, skc = (tid & 3) * 8;
+  const int64_t am = m0 + srow, bcol = n0 + srow;
+  const bool a_in = am < g.M, b_in = bcol < g.N;
+  // implicit im2col: the pixel of this thread's A row
+  const uint16_t *im_base = nullptr;
+  int im_h = 0, im_w = 0;
+  if (g.im_x) {
+    const int64_t m = min(am, (int64_t)g.M - 1);
+    const int HH = g.im_H * g.im_H;
+    const int64_t n = m / HH;
+    const int hw = (int)(m - n * HH);
+    im_h = hw / g.im_H;
+    im_w = hw - im_h * g.im_H;
+    im_base = g.im_x + n * g.im_sn;
+  }
+  // vector forms, decided once per launch
+  const bool a_vec = g.im_x ? (g.im_C % 8 == 0 && g.im_sc == 1 && g.im_sh % 8 == 0 && g.im_sw % 8 == 0 &&
+                               g.im_sn % 8 == 0 && (reinterpret_cast<uintptr_t>(g.im_x) & 15) == 0)
+                            : (g.a_k == 1 && g.a_m % 8 == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0);
+  const bool b_vec = g.b_k == 1 && g.b_n % 8 == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
+
+  auto load_a = [&](int k0) -> u16x8 {
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int k = k0 + skc;
+    if (!a_in) return v;
+    if (g.im_x) {
+      if (a_vec && k + 8 <= k_end) {
+        const int tap = k / g.im_C, ch = k - tap * g.im_C;
+        const int hh = im_h + tap / 3 - 1, ww = im_w + tap % 3 - 1;
+        if (hh >= 0 && hh < g.im_H && ww >= 0 && ww < g.im_H)
+          v = *reinterpret_cast<const u16x8 *>(im_base + ch + hh * g.im_sh + ww * g.im_sw);
+        return v;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = k + i;
+        if (kk < k_end) {
+          const int tap = kk / g.im_C, ch = kk - tap * g.im_C;
+          const int hh = im_h + tap / 3 - 1, ww = im_w + tap % 3 - 1;
+          if (hh >= 0 && hh < g.im_H && ww >= 0 && ww < g.im_H)
+            v[i] = im_base[ch * g.im_sc + hh * g.im_sh + ww * g.im_sw];
+        }
+      }
+      return v;
+    }
+    if (a_vec && k + 8 <= k_end) return *reinterpret_cast<const u16x8 *>(g.A + am * g.a_m + k);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (k + i < k_end) v[i] = g.A[am * g.a_m + (int64_t)(k + i) * g.a_k];
+    return v;
+  };
+  auto load_b = [&](int k0) -> u16x8 {
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int k = k0 + skc;
+    if (!b_in) return v;
+    if (b_vec && k + 8 <= k_end) return *reinterpret_cast<const u16x8 *>(g.B + bcol * g.b_n + k);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (k + i < k_end) v[i] = g.B[(int64_t)(k + i) * g.b_k + bcol * g.b_n];
+    return v;
+  };
+
   f32x16 acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  // implicit im2col: the pixel of each of this thread's 4 A rows, once
-  const uint16_t *im_base[4];
-  int im_h[4], im_w[4];
-  if (g.im_x) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t m = min(m0 + (tid + u * 256) / kTK, (int64_t)g.M - 1);
-      const int HH = g.im_H * g.im_H;
-      const int64_t n = m / HH;
-      const int hw = (int)(m - n * HH);
-      im_h[u] = hw / g.im_H;
-      im_w[u] = hw - im_h[u] * g.im_H;
-      im_base[u] = g.im_x + n * g.im_sn;
-    }
-  }
+  u16x8 pa = load_a(k_begin), pb = load_b(k_begin);
   for (int k0 = k_begin; k0 < k_end; k0 += kTK) {
-    // stage A (64 x 16) and B (16 x 64): 4 elements of each per thread
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + u * 256;
-      const int r = e / kTK, c = e % kTK;
-      const int64_t m = m0 + r;
-      const int k = k0 + c;
-      if (g.im_x) {
-        uint16_t v = 0;
-        if (m < g.M && k < k_end) {
-          const int tap = k / g.im_C, ch = k - tap * g.im_C;
-          const int hh = im_h[u] + tap / 3 - 1, ww = im_w[u] + tap % 3 - 1;
-          if (hh >= 0 && hh < g.im_H && ww >= 0 && ww < g.im_H)
-            v = im_base[u][ch * g.im_sc + hh * g.im_sh + ww * g.im_sw];
-        }
-        As[r][c] = v;
-      } else {
-        As[r][c] = (m < g.M && k < k_end) ? g.A[m * g.a_m + (int64_t)k * g.a_k] : (uint16_t)0;
-      }
-      const int kr = e / kTN, nc = e % kTN;
-      const int64_t n = n0 + nc;
-      const int kb = k0 + kr;
-      Bs[kr][nc] = (n < g.N && kb < k_end) ? g.B[(int64_t)kb * g.b_k + n * g.b_n] : (uint16_t)0;
-    }
+    __syncthreads();  // the previous step's operands are read
+    *reinterpret_cast<u16x8 *>(&As[srow][skc]) = pa;
+    *reinterpret_cast<u16x8 *>(&Bt[srow][skc]) = pb;
     __syncthreads();
+    if (k0 + kTK < k_end) {
+      pa = load_a(k0 + kTK);
+      pb = load_b(k0 + kTK);
+    }
 #pragma unroll
     for (int ks = 0; ks < kTK; ks += 8) {
-      bf16x4 a, b;
       const int kk = ks + (lane >> 5) * 4;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = (short)As[wm + (lane & 31)][kk + i];
-        b[i] = (short)Bs[kk + i][wn + (lane & 31)];
-      }
+      const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&As[wm + (lane & 31)][kk]);
+      const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Bt[wn + (lane & 31)][kk]);
       acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
     }
-    __syncthreads();
   }
   // epilogue: lane holds column wn + lane%32, rows 8*(j/4) + 4*(lane/32) + j%4
   const int64_t n = n0 + wn + (lane & 31);
