@@ -18,7 +18,9 @@
 // work is a fixed sequence of five kernels (stage, dedisperse, stats, search,
 // look-back shift) that read their work from device job tables; the sequence
 // is captured once into a hipGraph and replayed, the host rewriting the job
-// tables between replays.  Beams are admitted against a device-memory budget;
+// tables between replays.  While a step's kernels run, each beam's next
+// pending block is copied to the device on a second stream, into the other of
+// the beam's two input buffers.  Beams are admitted against a device-memory budget;
 // a beam that does not fit waits in a queue (its blocks stay on the host) and
 // is admitted when finished beams release their memory.
 #include <algorithm>
@@ -107,6 +109,7 @@ __device__ __forceinline__ int find_by_item0(const Tab *t, int64_t b) {
 // written as uint16 pairs; positions inside the guard band are written twice.
 __global__ __launch_bounds__(256) void k_stage_ring(const StageTable *__restrict__ tb) {
   __shared__ uint16_t tile[kStageTile * (kStageTile + 1)];
+  constexpr int TP = kStageTile + 1;
   const int tid = threadIdx.x;
   const int64_t n_items = tb->n_items;
   for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
@@ -116,26 +119,77 @@ __global__ __launch_bounds__(256) void k_stage_ring(const StageTable *__restrict
     const int64_t tt = local / J.c_tiles;
     const int64_t j0 = tt * kStageTile;
     const int c0 = ct * kStageTile;
-    for (int u = tid; u < kStageTile * kStageTile; u += 256) {
-      const int cl = u % kStageTile, jl = u / kStageTile;
+    if ((J.nchan & 15) == 0) {
+      // 16 channels of 4 outputs per thread: one 16-byte load per raw
+      // spectrum, the D spectra summed as 16-bit pairs (even bytes and odd
+      // bytes of each dword apart; D * 255 stays below 2^16)
+      static_assert(kStageTile == 128, "8 threads x 16 channels per output, 32 outputs per pass");
+      const int cl = 16 * (tid & 7);
       const int c = c0 + cl;
-      const int64_t j = j0 + jl;
-      uint32_t acc = 0;
-      if (c < J.nchan && j < J.n_new) {
-        const uint8_t *p = J.X + (j * J.D) * (int64_t)J.nchan + c;
-        for (int m = 0; m < J.D; ++m) acc += p[(int64_t)m * J.nchan];
+      const int jl = tid >> 3;
+      uint32_t ev[4][4], od[4][4];
+      bool ok[4];
+      const uint8_t *p[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t j = j0 + jl + 32 * i;
+        ok[i] = c < J.nchan && j < J.n_new;
+        p[i] = J.X + (j * J.D) * (int64_t)J.nchan + c;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) ev[i][d] = od[i][d] = 0;
       }
-      tile[cl * (kStageTile + 1) + jl] = (uint16_t)acc;
+      for (int m = 0; m < J.D; ++m) {
+        uint4 w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          w[i] = ok[i] ? *reinterpret_cast<const uint4 *>(p[i] + (int64_t)m * J.nchan) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t v[4] = {w[i].x, w[i].y, w[i].z, w[i].w};
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            ev[i][d] += v[d] & 0x00FF00FFu;         // channels 4d, 4d+2
+            od[i][d] += (v[d] >> 8) & 0x00FF00FFu;  // channels 4d+1, 4d+3
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        uint16_t *t = tile + cl * TP + jl + 32 * i;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          t[(4 * d + 0) * TP] = (uint16_t)ev[i][d];
+          t[(4 * d + 1) * TP] = (uint16_t)od[i][d];
+          t[(4 * d + 2) * TP] = (uint16_t)(ev[i][d] >> 16);
+          t[(4 * d + 3) * TP] = (uint16_t)(od[i][d] >> 16);
+        }
+      }
+    } else {
+      for (int u = tid; u < kStageTile * kStageTile; u += 256) {
+        const int cl = u % kStageTile, jl = u / kStageTile;
+        const int c = c0 + cl;
+        const int64_t j = j0 + jl;
+        uint32_t acc = 0;
+        if (c < J.nchan && j < J.n_new) {
+          const uint8_t *p = J.X + (j * J.D) * (int64_t)J.nchan + c;
+          for (int m = 0; m < J.D; ++m) acc += p[(int64_t)m * J.nchan];
+        }
+        tile[cl * TP + jl] = (uint16_t)acc;
+      }
     }
     __syncthreads();
+    // ring position of output j0 (even: phys0, j0 and ring are even); the
+    // ring holds more than kStageTile samples, so j0 + 2q wraps at most once
+    const int64_t pos0 = (J.phys0 + j0) % J.ring;
     for (int idx = tid; idx < kStageTile * (kStageTile / 2); idx += 256) {
       const int cl = idx / (kStageTile / 2);
       const int q = idx % (kStageTile / 2);
       const int c = c0 + cl;
       const int64_t j = j0 + 2 * q;
       if (c >= J.nchan || j >= J.n_new) continue;
-      int64_t pos = (J.phys0 + j) % J.ring;  // even: phys0 and ring are even
-      const uint16_t *t = tile + cl * (kStageTile + 1) + 2 * q;
+      int64_t pos = pos0 + 2 * q;
+      if (pos >= J.ring) pos -= J.ring;
+      const uint16_t *t = tile + cl * TP + 2 * q;
       uint16_t *row = J.Y + (int64_t)c * J.pitch;
       if (j + 1 < J.n_new) {
         const uint32_t v = (uint32_t)t[0] | ((uint32_t)t[1] << 16);
@@ -151,11 +205,24 @@ __global__ __launch_bounds__(256) void k_stage_ring(const StageTable *__restrict
 }
 
 // Dedispersion of every active (beam, row) window: grid-stride over tiles.
+// Workgroup x runs on XCD x % 8.  The tiles are cut into 8 contiguous
+// ranges, one per XCD, and each XCD's workgroups stride through their own
+// range, so the tiles in flight on one XCD are neighbouring DM tiles of the
+// same samples, whose staged windows overlap in that XCD's L2.
+// (at most 128 VGPRs, as the batch kernel: two workgroups of 8 waves per CU)
 template <int K, int TPW>
-__global__ __launch_bounds__(512) void k_dedisp_jobs(const DedispTable *__restrict__ tb) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dedisp_jobs(
+    const DedispTable *__restrict__ tb) {
   extern __shared__ uint32_t lds[];
   const int64_t n_items = tb->n_items;
-  for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
+  int64_t first = blockIdx.x, end = n_items, stride = gridDim.x;
+  if ((gridDim.x & 7) == 0) {
+    const int x = blockIdx.x & 7;
+    end = n_items * (x + 1) / 8;
+    first = n_items * x / 8 + (blockIdx.x >> 3);
+    stride = gridDim.x >> 3;
+  }
+  for (int64_t b = first; b < end; b += stride) {
     const int j = __builtin_amdgcn_readfirstlane(find_by_item0(tb, b));
     const DedispArgs a = tb->job[j].a;
     const int64_t local = b - tb->job[j].item0;
@@ -231,7 +298,12 @@ struct Beam {
   std::vector<gsp_segment> segs;
   gsp_dmt_desc desc;  // shaped with a nominal length: delays and maximum delays
   std::vector<std::unique_ptr<StreamRow>> rows;
-  DevBuf in;          // uint8 [B][nchan]
+  // uint8 [B][nchan] x 2: the current block, and the next one copied on the
+  // copy stream while the current step's kernels run
+  DevBuf in[2];
+  int cur = 0;                     // buffer holding the block being processed
+  const void *pf_src = nullptr;    // pinned host block copied into in[pf_buf] (null: none)
+  int pf_buf = 0;
   std::deque<PendingBlock> pending;
   int64_t blocks_done = 0;
   int64_t samples_in = 0;
@@ -247,6 +319,7 @@ struct Beam {
 struct gsp_stream {
   gsp_ctx *ctx = nullptr;
   hipStream_t st = nullptr;
+  hipStream_t cst = nullptr;  // copies of the next step's blocks
   int32_t B = 0;
   int64_t budget = 0, used = 0;
   std::vector<int32_t> widths;
@@ -316,7 +389,7 @@ void give_pinned(gsp_stream *s, PinnedBlock b) {
 }
 
 int64_t beam_bytes(const gsp_stream *s, const Beam &b) {
-  int64_t m = (int64_t)s->B * b.nchan;
+  int64_t m = 2 * (int64_t)s->B * b.nchan;
   for (const auto &r : b.rows) {
     m += (int64_t)b.nchan * (r->R + kGuard) * 2;
     m += (int64_t)r->n_dm * (s->look + r->Wcap) * 4;
@@ -355,8 +428,11 @@ void plan_beam(gsp_stream *s, Beam &b) {
 }
 
 void admit(gsp_stream *s, Beam &b) {
-  b.in.device = s->ctx->device;
-  b.in.reserve((size_t)s->B * b.nchan);
+  for (auto &in : b.in) {
+    in.device = s->ctx->device;
+    in.reserve((size_t)s->B * b.nchan);
+  }
+  b.pf_src = nullptr;
   for (auto &r : b.rows) {
     r->ring.device = s->ctx->device;
     r->ring.reserve((size_t)b.nchan * (r->R + kGuard) * 2);
@@ -374,7 +450,9 @@ void admit(gsp_stream *s, Beam &b) {
 
 void release(gsp_stream *s, Beam &b) {
   if (!b.admitted) return;
-  b.in.reserve(0);
+  check_hip(hipStreamSynchronize(s->cst), "synchronise copy stream");  // no copy still writes b.in
+  b.pf_src = nullptr;
+  for (auto &in : b.in) in.reserve(0);
   s->used -= b.mem;
   b.admitted = false;
 }
@@ -441,6 +519,9 @@ int64_t step_once(gsp_stream *s) {
   if (work.empty()) return 0;
   const auto t_start = Clock::now();
   hipStream_t st = s->st;
+  // blocks copied ahead during the previous step have arrived; from here on
+  // neither input buffer of any beam is being written or read
+  check_hip(hipStreamSynchronize(s->cst), "synchronise copy stream");
   StageTable &ts = *s->h_stage;
   DedispTable &td = *s->h_dedisp;
   SeriesTable &tr = *s->h_series;
@@ -461,8 +542,14 @@ int64_t step_once(gsp_stream *s) {
   std::vector<JobRef> series_refs;
   for (auto &w : work) {
     Beam &b = *w.b;
-    check_hip(hipMemcpyAsync(b.in.ptr, w.blk.buf.p, (size_t)w.blk.nsamp * b.nchan, hipMemcpyHostToDevice, st),
-              "copy block");
+    if (b.pf_src != nullptr && b.pf_src == w.blk.buf.p) {
+      b.cur = b.pf_buf;  // copied during the previous step
+    } else {
+      b.cur = 0;  // both buffers are idle here
+      check_hip(hipMemcpyAsync(b.in[0].ptr, w.blk.buf.p, (size_t)w.blk.nsamp * b.nchan, hipMemcpyHostToDevice, st),
+                "copy block");
+    }
+    b.pf_src = nullptr;
     for (int32_t r = 0; r < (int32_t)b.rows.size(); ++r) {
       StreamRow &R = *b.rows[r];
       const int64_t n_new = w.blk.nsamp / R.D;
@@ -470,7 +557,7 @@ int64_t step_once(gsp_stream *s) {
       if (n_new > 0) {
         if (ts.n_jobs >= kMaxJobs) fail(GSP_ECAPACITY, "too many streaming jobs");
         StageJob &J = ts.job[ts.n_jobs++];
-        J.X = b.in.as<uint8_t>();
+        J.X = b.in[b.cur].as<uint8_t>();
         J.Y = R.ring.as<uint16_t>();
         J.pitch = R.R + kGuard;
         J.ring = R.R;
@@ -588,6 +675,22 @@ int64_t step_once(gsp_stream *s) {
   } else {
     set_attributes(s, lds_need);
     launch_sequence(s, lds_need);
+  }
+  // while the kernels run, copy each beam's next pending block into its other
+  // input buffer (the front of a beam's queue only leaves it through a step,
+  // so that block is the one the next step takes)
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto &w : work) {
+      Beam &b = *w.b;
+      if (b.pending.empty()) continue;
+      const PendingBlock &nx = b.pending.front();
+      const int v = b.cur ^ 1;
+      check_hip(hipMemcpyAsync(b.in[v].ptr, nx.buf.p, (size_t)nx.nsamp * b.nchan, hipMemcpyHostToDevice, s->cst),
+                "copy next block");
+      b.pf_src = nx.buf.p;
+      b.pf_buf = v;
+    }
   }
   // results
   unsigned long long count = 0;
@@ -759,6 +862,7 @@ int gsp_stream_create(gsp_ctx *ctx, int64_t mem_budget_bytes, int32_t block_nsam
     s->tiling = search_tiling(s->wmax);
     if ((int64_t)s->look * 4 > 64 * 1024) fail(GSP_EINVAL, "widths too large for the look-back shift");
     check_hip(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "create stream");
+    check_hip(hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking), "create copy stream");
     for (DevBuf *d : {&s->d_stage, &s->d_dedisp, &s->d_series, &s->d_tail, &s->d_widths, &s->musig, &s->frags,
                       &s->counter, &s->d_cuts, &s->d_cutimg, &s->d_logits})
       d->device = ctx->device;
@@ -782,6 +886,7 @@ void gsp_stream_destroy(gsp_stream *s) {
   gsp_stream_stop(s);
   (void)hipSetDevice(s->ctx->device);
   (void)hipStreamSynchronize(s->st);
+  (void)hipStreamSynchronize(s->cst);
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   for (auto &kv : s->beams)
@@ -789,6 +894,7 @@ void gsp_stream_destroy(gsp_stream *s) {
   for (auto &p : s->pool) (void)hipHostFree(p.p);
   s->beams.clear();
   (void)hipStreamDestroy(s->st);
+  (void)hipStreamDestroy(s->cst);
   delete s;
 }
 

@@ -85,13 +85,21 @@ def run_beams(env, beams, interleave=True, graph=True, budget=1 << 34, check_win
     return ids, cands, rep
 
 
-def test_single_beam_windows_and_candidates_match_oracle(env):
+# 64 channels: one channel tile staged 16 channels per thread; 40: not a
+# multiple of 16, staged one channel per thread; 160: two channel tiles, the
+# second partly empty, and a D = 4 row
+SINGLE = [dict(nchan=64), dict(nchan=40), dict(nchan=160, segs=[(0.0, 1.0, 40, 1), (40.0, 2.0, 13, 2),
+                                                                   (66.0, 4.0, 8, 4)])]
+
+
+@pytest.mark.parametrize("cfg", SINGLE, ids=lambda c: f"nchan{c['nchan']}")
+def test_single_beam_windows_and_candidates_match_oracle(env, cfg):
     gsp, ctx, torch = env
-    w = beam_workload(0, nsamp=3000)
+    w = beam_workload(0, nsamp=3000, **cfg)
     X = w.generate()
     full = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
     wins = windows_of(w)
-    say(f"[case] single beam, windows {wins}")
+    say(f"[case] single beam, {cfg}, windows {wins}")
     seen = []
 
     def check(s, ids, k):
