@@ -300,3 +300,52 @@ def test_triage_threshold_filters_and_detaches(env):
     s.close()
     assert len(got) == 0 and rep["triage_rejected"] == rep["triage_scored"] == len(plain)
     net.close()
+
+
+def test_full_shape_windows_equal_batch_and_oracle(env):
+    """One beam of the streaming workload's shape (4096 channels over
+    1000-1500 MHz, tsamp 49.152 us, blocks of 20480 samples; the ladder's
+    four rows D = 1, 2, 4, 8 cut to 100-200 trials each), every block pushed
+    before the first step so that each step's next block is copied during the
+    step: after every step each row's window equals the batch dedispersion of
+    the whole beam over the same outputs, bit for bit, and 40 sampled outputs
+    per window equal the oracle's."""
+    gsp, ctx, torch = env
+    B = 20480
+    segs = [(0.0, 0.1, 200, 1), (150.0, 0.3, 100, 2), (450.0, 1.0, 100, 4), (1200.0, 3.0, 100, 8)]
+    w = synth.Workload("stream-shape", 4096, 1000.0, 1500.0, 49.152e-6, 8 * B, segs, synth.WIDTHS_512, 6.0,
+                       synth.BASE_SEED + 7)
+    say("[case] full-shape stream beam: generate")
+    X = w.generate()
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    dmt = ctx.dedisperse(torch.from_numpy(X).to("cuda"), w.freqs, desc)
+    views = gsp.segment_views(desc, dmt)
+    max_delay, n_out = oracle.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    s = gsp.Stream(ctx, 1 << 34, B, synth.WIDTHS_512, 6.0)
+    bid, ok = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
+    assert ok
+    for k in range(w.nsamp // B):
+        s.push(bid, X[k * B:(k + 1) * B])
+    rng = np.random.default_rng(3)
+    checked = 0
+    for k in range(w.nsamp // B):
+        assert s.step() == 1
+        for r, seg in enumerate(segs):
+            D, M = seg[3], int(max_delay[r])
+            a, b = max(0, k * B // D - M), max(0, (k + 1) * B // D - M)
+            t0, arr = s.window(bid, r, seg[2])
+            assert (t0, arr.shape[1]) == (a, b - a), (k, r)
+            if b == a:
+                continue
+            ref = views[r][:, a:b].cpu().numpy()
+            assert (arr == ref).all(), (k, r)
+            tr = rng.integers(0, seg[2], 40)
+            tt = rng.integers(a, b, 40)
+            pts = oracle.dedisperse_points(X, w.freqs, w.tsamp, seg, tr, tt)
+            assert (arr[tr, tt - a].astype(np.int64) == pts).all(), (k, r)
+            checked += b - a
+        say(f"  step {k}: windows checked")
+    assert checked == int(sum(n_out))  # every output of every row, once
+    s.close()
+    del dmt
+    torch.cuda.empty_cache()
