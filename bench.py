@@ -306,8 +306,10 @@ def main():
         log(f"autotune: {shapes} in {time.perf_counter() - t:.1f} s")
 
     net = None if args.no_cnn else gsp.Cnn(ctx, seed=1)
-    cut = torch.empty((4096, 2, 64, 64), dtype=torch.int16, device="cuda:0")
-    logits = torch.empty(4096, dtype=torch.float32, device="cuda:0")
+    # room for 16384 events per network call (an event-richer step is cut out
+    # and scored in chunks of that many)
+    cut = torch.empty((16384, 2, 64, 64), dtype=torch.int16, device="cuda:0")
+    logits = torch.empty(16384, dtype=torch.float32, device="cuda:0")
     t_triage = [0.0]
 
     def step():
@@ -317,10 +319,14 @@ def main():
         if net is not None and ng:
             # triage: cutouts of each event's representative, network scores
             t = time.perf_counter()
-            ev = c[rep][:cut.shape[0]]
-            x = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, ev, out=cut[:len(ev)], stream=stream)
-            net.forward(x, out=logits[:len(ev)], stream=stream)
-            keep = int((logits[:len(ev)] > 0).sum().item())
+            ev = c[np.unique(rep)]  # one candidate per event: its max-SNR member
+            keep = 0
+            for e0 in range(0, len(ev), cut.shape[0]):
+                part = ev[e0:e0 + cut.shape[0]]
+                x = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, part, out=cut[:len(part)], stream=stream)
+                net.forward(x, out=logits[:len(part)], stream=stream)
+                keep += int((logits[:len(part)] > 0).sum().item())
+            assert len(ev) == ng
             t_triage[0] += time.perf_counter() - t
         return c, ng
 
