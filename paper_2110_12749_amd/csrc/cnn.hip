@@ -570,24 +570,42 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
     // Tiled band sums: the band's raw rows for a run of bins are read as
     // 16-byte row segments (a few cache lines per load instead of one per
     // channel) into the wave's LDS tile, then each lane sums its channel's
-    // shifted rows from there.  Applies when bands are whole 16-byte
-    // segments and the rows of at least one bin plus the band's delay
-    // spread fit the tile.
+    // shifted rows from there.  The band's channels go through in groups of
+    // G = 64, 32 or 16, the widest for which every group's delay spread plus
+    // one bin fits the tile (a narrower group has a smaller spread and its
+    // G-byte rows leave room for more of them; lanes G..63 add nothing).
+    // Applies when bands are whole 16-byte segments.
     auto band_sums = [&](int band, int cb, int ce, int64_t e, int r, uint32_t &mine) -> bool {
       if (!a.tiled) return false;
-      int dmin = INT_MAX, dmax = INT_MIN;
-      for (int g0 = cb; g0 < ce; g0 += 64) {
+      auto spread_of = [&](int g0, int G) {
         const int ch = g0 + lane;
-        dmin = min(dmin, wave_min_i32(ch < ce ? dly[ch] : INT_MAX));
-        dmax = max(dmax, wave_max_i32(ch < ce ? dly[ch] : INT_MIN));
+        const bool in = lane < G && ch < ce;
+        const int lo = wave_min_i32(in ? dly[ch] : INT_MAX);
+        const int hi = wave_max_i32(in ? dly[ch] : INT_MIN);
+        return make_int2(lo, hi);
+      };
+      int gmax = 64;  // no wider than the band (bands are multiples of 16 channels)
+      while (gmax > 16 && gmax / 2 >= ce - cb) gmax >>= 1;
+      int G = 0;
+      for (int g = gmax; g >= 16 && G == 0; g >>= 1) {
+        const int64_t cap = (int64_t)kTileRows * 64 / g / D;  // downsampled rows the tile holds
+        bool fits = true;
+        for (int g0 = cb; g0 < ce && fits; g0 += g) {
+          const auto lh = spread_of(g0, g);
+          fits = (cap - ((int64_t)lh.y - lh.x)) / r >= 1;
+        }
+        if (fits) G = g;
       }
-      const int64_t spread = (int64_t)dmax - dmin;
-      const int64_t nb = ((int64_t)kTileRows / D - spread) / r;
-      if (nb < 1) return false;
+      if (G == 0) return false;
+      const int lq = G == 64 ? 2 : G == 32 ? 1 : 0;  // log2 of the 16-byte segments per row
+      const int64_t cap = (int64_t)kTileRows * 64 / G / D;
       const int64_t t0 = e - 64 * (int64_t)r + 1;
-      for (int g0 = cb; g0 < ce; g0 += 64) {
+      for (int g0 = cb; g0 < ce; g0 += G) {
         const int ch = g0 + lane;
-        const bool valid = ch < ce;
+        const bool valid = lane < G && ch < ce;
+        const auto lh = spread_of(g0, G);
+        const int dmin = lh.x, dmax = lh.y;
+        const int64_t nb = (cap - ((int64_t)dmax - dmin)) / r;  // >= 1 (G was chosen so)
         const int64_t dc = valid ? dly[ch] : dmin;
         for (int b0 = 0; b0 < 64; b0 += (int)nb) {
           const int b1 = (int)min((int64_t)64, b0 + nb);
@@ -595,22 +613,23 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
           const int64_t s_lo = max(t0 + (int64_t)b0 * r, (int64_t)0) + dmin;
           const int64_t s_hi = t0 + (int64_t)b1 * r - 1 + dmax;
           const int64_t R0 = s_lo * D;
-          const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= kTileRows
+          const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= cap * D: nrows * G bytes fit the tile
+          const int nseg = nrows << lq;
           __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
           // 8 loads in flight per lane before their LDS stores
-          for (int i0 = lane; i0 < nrows * 4; i0 += 64 * 8) {
+          for (int i0 = lane; i0 < nseg; i0 += 64 * 8) {
             uint4 v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-              const int i = min(i0 + 64 * u, nrows * 4 - 1);
-              const int q = i & 3;
-              v[u] = g0 + 16 * q < ce ? *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> 2)) * (int64_t)nchan + g0 + 16 * q)
+              const int i = min(i0 + 64 * u, nseg - 1);
+              const int q = i & ((1 << lq) - 1);
+              v[u] = g0 + 16 * q < ce ? *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> lq)) * (int64_t)nchan + g0 + 16 * q)
                                       : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const int i = i0 + 64 * u;
-              if (i < nrows * 4) tile4[i] = v[u];
+              if (i < nseg) tile4[i] = v[u];
             }
           }
           __builtin_amdgcn_wave_barrier();
@@ -619,9 +638,9 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
             const int jlo = (int)max((int64_t)0, -tb);
             uint32_t s = 0;
             if (jlo < r && valid) {
-              const uint8_t *p = tileb + ((tb + jlo + dc) * D - R0) * 64 + (ch - g0);
+              const uint8_t *p = tileb + ((tb + jlo + dc) * D - R0) * G + (ch - g0);
               const int nu = (r - jlo) * D;
-              for (int u = 0; u < nu; ++u) s += p[u * 64];
+              for (int u = 0; u < nu; ++u) s += p[u * G];
             }
             const uint32_t tot = wave_sum_u32(s);
             if (lane == b) mine += tot;

@@ -250,6 +250,21 @@ def test_cutouts_tiled_bands(env, nchan):
     cutout_case(env, w, extra)
 
 
+def test_cutouts_tiled_bands_high_dm(env):
+    """Realistic sampling (4096 channels over 1000-1500 MHz, tsamp 49.152 us)
+    at high DM, where a 64-channel band's delay spread plus a bin no longer
+    fits the tile: the kernel stages such bands in 32-channel groups (D = 4
+    row near DM 600: 199 samples of spread at the bottom of the band) or
+    16-channel groups (D = 8 row near DM 1500: 247 samples), and the upper
+    bands still in 64-channel groups."""
+    segs = [(600.0, 1.0, 16, 4), (1480.0, 3.0, 12, 8)]
+    w = synth.small(nchan=4096, nsamp=90000, segments=segs, tsamp=49.152e-6, n_pulses=2, seed_offset=91,
+                    widths=[1, 2, 4, 8, 16, 32, 64])
+    # (row, trial, t_peak, width) inside their rows (n_out 15288 and 2378)
+    extra = [(0, 5, 3000, 64), (0, 15, 100, 8), (1, 6, 2000, 64), (1, 0, 10, 16), (1, 11, 2300, 8)]
+    cutout_case(env, w, extra)
+
+
 def test_cutouts_invalid_candidates_give_zero_images(env):
     gsp, ctx, torch = env
     w = synth.tiny()
