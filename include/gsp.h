@@ -323,7 +323,10 @@ int gsp_profile_read(gsp_ctx *ctx, gsp_kernel_stat *out, int32_t cap, int32_t *n
  * output for this filterbank).  cands_dev: device gsp_candidate[n] (as
  * returned by the search, copied to the device); a candidate whose row,
  * trial or box end lies outside the plan gets two zero images.  out_dev: device
- * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`. */
+ * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`.  The context keeps
+ * a device buffer of 16 KB per candidate for the frequency-time band sums
+ * (grown, with a device synchronisation, when a call has more candidates
+ * than any before it). */
 int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const int32_t *dmt_dev,
                 const gsp_dmt_desc *desc, const gsp_candidate *cands_dev, int64_t n, uint16_t *out_dev,
                 void *stream);

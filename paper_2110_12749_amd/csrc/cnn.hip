@@ -368,6 +368,7 @@ struct CutoutArgs {
   int32_t tiled;      // bands are 16-byte aligned row segments (nchan % 1024 == 0, fb 16-byte aligned)
   CutRow row[GSP_MAX_SEG];
   uint16_t *out;  // bf16 [n][2][64][64]
+  uint32_t *ftsums;  // [n][64 bands][64 bins]: frequency-time band sums (k_cutout_ft writes, k_cutout reads)
 };
 
 // Sum of a uint32 over the 64 lanes of a wave (DPP shifts inside rows of 16,
@@ -537,13 +538,147 @@ __device__ __forceinline__ int wave_max_i32(int v) {
   return v;
 }
 
+// Tiled band sums of one frequency-time band: the band's raw rows for a run
+// of bins are read as 16-byte row segments (a few cache lines per load
+// instead of one per channel) into the wave's LDS tile, then each lane sums
+// its channel's shifted rows from there and bin b's total over the lanes is
+// added to `mine` on lane b.  The band's channels go through in groups of
+// G = 64, 32 or 16, the widest for which every group's delay spread plus one
+// bin fits the tile (a narrower group has a smaller spread and its G-byte
+// rows leave room for more of them; lanes G..63 add nothing).  Needs bands
+// of whole 16-byte segments; false where no group width fits.
+__device__ bool tiled_band_sums(const uint8_t *__restrict__ fb, int nchan, int D, const int32_t *__restrict__ dly,
+                                int cb, int ce, int64_t e, int r, uint4 *tile4, uint32_t &mine) {
+  const int lane = threadIdx.x & 63;
+  const uint8_t *tileb = reinterpret_cast<const uint8_t *>(tile4);
+  auto spread_of = [&](int g0, int G) {
+    const int ch = g0 + lane;
+    const bool in = lane < G && ch < ce;
+    const int lo = wave_min_i32(in ? dly[ch] : INT_MAX);
+    const int hi = wave_max_i32(in ? dly[ch] : INT_MIN);
+    return make_int2(lo, hi);
+  };
+  int gmax = 64;  // no wider than the band (bands are multiples of 16 channels)
+  while (gmax > 16 && gmax / 2 >= ce - cb) gmax >>= 1;
+  int G = 0;
+  for (int g = gmax; g >= 16 && G == 0; g >>= 1) {
+    const int64_t cap = (int64_t)kTileRows * 64 / g / D;  // downsampled rows the tile holds
+    bool fits = true;
+    for (int g0 = cb; g0 < ce && fits; g0 += g) {
+      const auto lh = spread_of(g0, g);
+      fits = (cap - ((int64_t)lh.y - lh.x)) / r >= 1;
+    }
+    if (fits) G = g;
+  }
+  if (G == 0) return false;
+  const int lq = G == 64 ? 2 : G == 32 ? 1 : 0;  // log2 of the 16-byte segments per row
+  const int64_t cap = (int64_t)kTileRows * 64 / G / D;
+  const int64_t t0 = e - 64 * (int64_t)r + 1;
+  for (int g0 = cb; g0 < ce; g0 += G) {
+    const int ch = g0 + lane;
+    const bool valid = lane < G && ch < ce;
+    const auto lh = spread_of(g0, G);
+    const int dmin = lh.x, dmax = lh.y;
+    const int64_t nb = (cap - ((int64_t)dmax - dmin)) / r;  // >= 1 (G was chosen so)
+    const int64_t dc = valid ? dly[ch] : dmin;
+    for (int b0 = 0; b0 < 64; b0 += (int)nb) {
+      const int b1 = (int)min((int64_t)64, b0 + nb);
+      if (t0 + (int64_t)b1 * r - 1 < 0) continue;  // these bins lie before the first sample
+      const int64_t s_lo = max(t0 + (int64_t)b0 * r, (int64_t)0) + dmin;
+      const int64_t s_hi = t0 + (int64_t)b1 * r - 1 + dmax;
+      const int64_t R0 = s_lo * D;
+      const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= cap * D: nrows * G bytes fit the tile
+      const int nseg = nrows << lq;
+      __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
+      // 8 loads in flight per lane before their LDS stores
+      for (int i0 = lane; i0 < nseg; i0 += 64 * 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = min(i0 + 64 * u, nseg - 1);
+          const int q = i & ((1 << lq) - 1);
+          v[u] = g0 + 16 * q < ce ? *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> lq)) * (int64_t)nchan + g0 + 16 * q)
+                                  : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < nseg) tile4[i] = v[u];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int b = b0; b < b1; ++b) {
+        const int64_t tb = t0 + (int64_t)b * r;
+        const int jlo = (int)max((int64_t)0, -tb);
+        uint32_t s = 0;
+        if (jlo < r && valid) {
+          const uint8_t *p = tileb + ((tb + jlo + dc) * D - R0) * G + (ch - g0);
+          const int nu = (r - jlo) * D;
+          for (int u = 0; u < nu; ++u) s += p[u * G];
+        }
+        const uint32_t tot = wave_sum_u32(s);
+        if (lane == b) mine += tot;
+      }
+    }
+  }
+  return true;
+}
+
+// Frequency-time band sums of batch cutouts, one wave per (event, band): the
+// band's bins summed over its channels as exact integers (lane b: bin b),
+// written for k_cutout, which scales partial bins and z-scores.  Apart from
+// the images this kernel holds only the row tiles in LDS, so several
+// workgroups share a CU.
+__global__ __launch_bounds__(256) void k_cutout_ft(CutoutArgs a) {
+  __shared__ uint4 tiles[4][kTileRows * 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t item = blockIdx.x; item < a.n * 16; item += gridDim.x) {
+    const int64_t k = item >> 4;
+    const int band = (int)(item & 15) * 4 + wave;
+    const gsp_candidate c = a.cand[k];
+    const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
+                    c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
+                    c.t_peak + c.width - 1 < a.row[c.seg].n_out;
+    if (!ok) continue;  // k_cutout writes zero images and reads nothing here
+    const CutRow R = a.row[c.seg];
+    const int nchan = a.nchan, D = R.D;
+    const int32_t *dly = R.delays + (int64_t)c.dm_index * nchan;
+    const int64_t e = c.t_peak + c.width - 1;
+    const int r = max(1, min(a.rmax, c.width / 8));
+    const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
+    uint32_t mine = 0;
+    if (!(a.tiled && tiled_band_sums(a.fb, nchan, D, dly, cb, ce, e, r, tiles[wave], mine))) {
+      // every lane reads its channels' bytes directly
+      uint32_t acc[64];
+#pragma unroll
+      for (int b = 0; b < 64; ++b) acc[b] = 0;
+      for (int ch = cb + lane; ch < ce; ch += 64)
+        for (int j = 0; j < r; ++j) {
+#pragma unroll
+          for (int b = 0; b < 64; ++b) {
+            const int64_t t = e - (int64_t)(64 - b) * r + 1 + j;
+            if (t >= 0) {
+              const uint8_t *p = a.fb + ((t + dly[ch]) * D) * (int64_t)nchan + ch;
+              uint32_t v = 0;
+              for (int m = 0; m < D; ++m) v += p[(int64_t)m * nchan];
+              acc[b] += v;
+            }
+          }
+        }
+#pragma unroll
+      for (int b = 0; b < 64; ++b) {
+        const uint32_t tot = wave_sum_u32(acc[b]);
+        if (lane == b) mine = tot;
+      }
+    }
+    a.ftsums[(k * 64 + band) * 64 + lane] = mine;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
   __shared__ double img[2][64 * 64];
   __shared__ double red[3][256];
-  __shared__ uint4 tiles[4][kTileRows * 4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint4 *tile4 = tiles[wave];
-  const uint8_t *tileb = reinterpret_cast<const uint8_t *>(tiles[wave]);
+  const int tid = threadIdx.x, lane = tid & 63;
   for (int64_t k = blockIdx.x; k < a.n; k += gridDim.x) {
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
@@ -567,86 +702,9 @@ __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
       for (int m = 0; m < D; ++m) v += p[(int64_t)m * nchan];
       return v;
     };
-    // Tiled band sums: the band's raw rows for a run of bins are read as
-    // 16-byte row segments (a few cache lines per load instead of one per
-    // channel) into the wave's LDS tile, then each lane sums its channel's
-    // shifted rows from there.  The band's channels go through in groups of
-    // G = 64, 32 or 16, the widest for which every group's delay spread plus
-    // one bin fits the tile (a narrower group has a smaller spread and its
-    // G-byte rows leave room for more of them; lanes G..63 add nothing).
-    // Applies when bands are whole 16-byte segments.
+    // the band sums come from k_cutout_ft
     auto band_sums = [&](int band, int cb, int ce, int64_t e, int r, uint32_t &mine) -> bool {
-      if (!a.tiled) return false;
-      auto spread_of = [&](int g0, int G) {
-        const int ch = g0 + lane;
-        const bool in = lane < G && ch < ce;
-        const int lo = wave_min_i32(in ? dly[ch] : INT_MAX);
-        const int hi = wave_max_i32(in ? dly[ch] : INT_MIN);
-        return make_int2(lo, hi);
-      };
-      int gmax = 64;  // no wider than the band (bands are multiples of 16 channels)
-      while (gmax > 16 && gmax / 2 >= ce - cb) gmax >>= 1;
-      int G = 0;
-      for (int g = gmax; g >= 16 && G == 0; g >>= 1) {
-        const int64_t cap = (int64_t)kTileRows * 64 / g / D;  // downsampled rows the tile holds
-        bool fits = true;
-        for (int g0 = cb; g0 < ce && fits; g0 += g) {
-          const auto lh = spread_of(g0, g);
-          fits = (cap - ((int64_t)lh.y - lh.x)) / r >= 1;
-        }
-        if (fits) G = g;
-      }
-      if (G == 0) return false;
-      const int lq = G == 64 ? 2 : G == 32 ? 1 : 0;  // log2 of the 16-byte segments per row
-      const int64_t cap = (int64_t)kTileRows * 64 / G / D;
-      const int64_t t0 = e - 64 * (int64_t)r + 1;
-      for (int g0 = cb; g0 < ce; g0 += G) {
-        const int ch = g0 + lane;
-        const bool valid = lane < G && ch < ce;
-        const auto lh = spread_of(g0, G);
-        const int dmin = lh.x, dmax = lh.y;
-        const int64_t nb = (cap - ((int64_t)dmax - dmin)) / r;  // >= 1 (G was chosen so)
-        const int64_t dc = valid ? dly[ch] : dmin;
-        for (int b0 = 0; b0 < 64; b0 += (int)nb) {
-          const int b1 = (int)min((int64_t)64, b0 + nb);
-          if (t0 + (int64_t)b1 * r - 1 < 0) continue;  // these bins lie before the first sample
-          const int64_t s_lo = max(t0 + (int64_t)b0 * r, (int64_t)0) + dmin;
-          const int64_t s_hi = t0 + (int64_t)b1 * r - 1 + dmax;
-          const int64_t R0 = s_lo * D;
-          const int nrows = (int)((s_hi - s_lo + 1) * D);  // <= cap * D: nrows * G bytes fit the tile
-          const int nseg = nrows << lq;
-          __builtin_amdgcn_wave_barrier();  // the previous pass's reads are done
-          // 8 loads in flight per lane before their LDS stores
-          for (int i0 = lane; i0 < nseg; i0 += 64 * 8) {
-            uint4 v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = min(i0 + 64 * u, nseg - 1);
-              const int q = i & ((1 << lq) - 1);
-              v[u] = g0 + 16 * q < ce ? *reinterpret_cast<const uint4 *>(fb + (R0 + (i >> lq)) * (int64_t)nchan + g0 + 16 * q)
-                                      : make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int i = i0 + 64 * u;
-              if (i < nseg) tile4[i] = v[u];
-            }
-          }
-          __builtin_amdgcn_wave_barrier();
-          for (int b = b0; b < b1; ++b) {
-            const int64_t tb = t0 + (int64_t)b * r;
-            const int jlo = (int)max((int64_t)0, -tb);
-            uint32_t s = 0;
-            if (jlo < r && valid) {
-              const uint8_t *p = tileb + ((tb + jlo + dc) * D - R0) * G + (ch - g0);
-              const int nu = (r - jlo) * D;
-              for (int u = 0; u < nu; ++u) s += p[u * G];
-            }
-            const uint32_t tot = wave_sum_u32(s);
-            if (lane == b) mine += tot;
-          }
-        }
-      }
+      mine = a.ftsums[((int64_t)k * 64 + band) * 64 + lane];
       return true;
     };
     cutout_images(c.t_peak + c.width - 1, c.width, c.dm_index, R.n_dm, nchan, a.rmax, dm, mean, ft, band_sums, img,
@@ -1178,6 +1236,10 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
       a.row[s].D = desc->seg[s].downsamp;
       a.row[s].trial0 = desc->trial0[s];
     }
+    ctx->ftsums.device = ctx->device;
+    ctx->ftsums.reserve((size_t)n * 64 * 64 * sizeof(uint32_t));
+    a.ftsums = ctx->ftsums.as<uint32_t>();
+    hipLaunchKernelGGL(k_cutout_ft, dim3((unsigned)std::min<int64_t>(n * 16, 256 * 64)), dim3(256), 0, st, a);
     const unsigned grid = (unsigned)std::min<int64_t>(n, 256 * 8);
     hipLaunchKernelGGL(k_cutout, dim3(grid), dim3(256), 0, st, a);
     check_hip(hipGetLastError(), "launch cutouts");

@@ -137,6 +137,7 @@ struct gsp_ctx {
   gsp::DevBuf counter;     // fragment counter
   gsp::DevBuf widths;      // device copy of the width set
   gsp::DevBuf jobs;        // device copy of the series-job table
+  gsp::DevBuf ftsums;      // frequency-time band sums of batch cutouts
   std::unique_ptr<gsp::SeriesTable> jobs_host = std::make_unique<gsp::SeriesTable>();
   std::vector<uint8_t> host_scratch;
   // tuned shapes keyed by row signature
