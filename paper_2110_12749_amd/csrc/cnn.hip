@@ -628,13 +628,19 @@ __device__ bool tiled_band_sums(const uint8_t *__restrict__ fb, int nchan, int D
 // band's bins summed over its channels as exact integers (lane b: bin b),
 // written for k_cutout, which scales partial bins and z-scores.  Apart from
 // the images this kernel holds only the row tiles in LDS, so several
-// workgroups share a CU.
+// workgroups share a CU.  Workgroup x runs on XCD x % 8 (the grid is a
+// multiple of 8); event k's 16 workgroups (4 bands each) all run on XCD
+// k % 8, whose workgroups take that XCD's events in order, so neighbouring
+// bands, which share cache lines of the filterbank rows, share an L2.
 __global__ __launch_bounds__(256) void k_cutout_ft(CutoutArgs a) {
   __shared__ uint4 tiles[4][kTileRows * 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t item = blockIdx.x; item < a.n * 16; item += gridDim.x) {
-    const int64_t k = item >> 4;
-    const int band = (int)(item & 15) * 4 + wave;
+  const int x = blockIdx.x & 7;
+  const int64_t per_xcd = gridDim.x >> 3;
+  for (int64_t j = blockIdx.x >> 3;; j += per_xcd) {
+    const int64_t k = (j >> 4) * 8 + x;
+    if (k >= a.n) break;
+    const int band = (int)(j & 15) * 4 + wave;
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
                     c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
@@ -1239,7 +1245,9 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     ctx->ftsums.device = ctx->device;
     ctx->ftsums.reserve((size_t)n * 64 * 64 * sizeof(uint32_t));
     a.ftsums = ctx->ftsums.as<uint32_t>();
-    hipLaunchKernelGGL(k_cutout_ft, dim3((unsigned)std::min<int64_t>(n * 16, 256 * 64)), dim3(256), 0, st, a);
+    // a multiple of 8 workgroups (the kernel's XCD mapping needs it)
+    hipLaunchKernelGGL(k_cutout_ft, dim3((unsigned)std::min<int64_t>((n + 7) / 8 * 8 * 16, 256 * 64)), dim3(256), 0,
+                       st, a);
     const unsigned grid = (unsigned)std::min<int64_t>(n, 256 * 8);
     hipLaunchKernelGGL(k_cutout, dim3(grid), dim3(256), 0, st, a);
     check_hip(hipGetLastError(), "launch cutouts");
