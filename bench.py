@@ -255,6 +255,8 @@ def main():
                     help="keep the default tile shapes (otherwise the autotuner picks one per row before the warm-up)")
     ap.add_argument("--shapes", action="store_true",
                     help="time a fixed set of dedispersion tile shapes on every row of the workload (markdown table)")
+    ap.add_argument("--rows", default=None,
+                    help="comma-separated plan rows to keep (e.g. 0 for the D = 1 row alone; profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -286,6 +288,9 @@ def main():
         del src, dst
 
     w = workload(args.workload)
+    if args.rows is not None:
+        keep = [int(r) for r in args.rows.split(",")]
+        w.segments = [w.segments[r] for r in keep]
     if args.shapes:
         shape_sweep(w)
         return
