@@ -9,19 +9,23 @@ The paper names the classification of candidates as a pipeline stage
 no classifier, no cutout and no training recipe: parity unpinned by the
 paper.  What is computed here is the plain definition of the network and
 cutouts declared in the library's header, pinned by mathematics instead:
-central finite differences of the loss (float64 mode), a library
-cross-correlation for the convolutions, closed forms of the loss, of Adam's
-first steps and of the pooling routing, brute-force loops on tiny inputs.
+central finite differences of the loss, torch's float64 layers and autograd,
+a library cross-correlation for the convolutions, closed forms of the loss,
+of Adam's first steps and of the pooling routing, brute-force loops on tiny
+inputs.
 
-Two modes of the same code:
-  exact=True   all arithmetic in float64, no storage rounding: a smooth
-               function of the parameters (between ReLU / max-pool pattern
-               changes), the one the finite-difference pins check;
-  exact=False  float64 arithmetic with bf16 rounding (nearest even) at every
-               point where the GPU stores bf16: input and weights, every
-               activation, the loss gradient and every backward activation
-               gradient.  Products are then accumulated in float64 where the
-               GPU accumulates in float32.
+The network is defined on bf16 numbers: its input images and its weights
+are bf16 values.  ``quantized=True`` rounds the given input and weights to
+bf16 (nearest even) and then computes every product, sum and nonlinearity
+of the forward and backward passes in float64, with no further rounding;
+``quantized=False`` rounds nothing (a smooth function of the parameters
+between ReLU / max-pool pattern changes, the one the finite-difference pins
+check).  Where an implementation stores an intermediate result at lower
+precision, its tests compare that stored value with the float64 one here.
+The layer functions (``conv_block``, ``conv_block_backward``, ``fc1``,
+``fc1_backward``, ``head_backward``) take their inputs explicitly so that a
+test can feed each layer the implementation's own stored input or upstream
+gradient.
 """
 from __future__ import annotations
 
@@ -109,22 +113,77 @@ def unpool2(dy, q, H, W):
     return out.reshape(N, C, H // 2, W // 2, 2, 2).transpose(0, 1, 2, 4, 3, 5).reshape(N, C, H, W)
 
 
-def forward(params, x, exact=False):
-    """x: [N][2][64][64] (values; bf16-rounded in the storage mode).
-    Returns (logits [N], cache)."""
-    r = (lambda a: a) if exact else bf16
-    P = {k: r(v) if k.endswith(".w") else v for k, v in unpack(params).items()}
-    a = r(np.asarray(x, dtype=np.float64))
+def conv_block(x, w, b):
+    """One convolution block: act = ReLU(conv3x3(x, w) + b), then a 2x2
+    max-pool.  Returns (act [N][O][H][W], pooled [N][O][H/2][W/2], q)."""
+    act = np.maximum(conv3x3(x, w, b), 0.0)
+    pooled, q = maxpool2(act)
+    return act, pooled, q
+
+
+def conv_block_backward(dpooled, x, w, act, q):
+    """Gradients of one block given the gradient of its pooled output:
+    dpre = (dpooled routed to the pooled positions q) * [act > 0];
+    dW[o,i,j,c] = sum_{n,h,v} dpre[n,o,h,v] x[n,c,h+i-1,v+j-1];
+    db[o] = sum dpre[n,o,h,v];
+    dx[n,c,h,v] = sum_{o,i,j} dpre[n,o,h-i+1,v-j+1] w[o,i,j,c].
+    Returns (dW, db, dx, dpre)."""
+    n, ci, H, _ = x.shape
+    dpre = unpool2(dpooled, q, H, H) * (act > 0)
+    xp = np.zeros((n, ci, H + 2, H + 2))
+    xp[:, :, 1:-1, 1:-1] = x
+    gw = np.zeros((w.shape[0], 3, 3, ci))
+    dxp = np.zeros((n, ci, H + 2, H + 2))
+    for i in range(3):
+        for j in range(3):
+            gw[:, i, j, :] = np.einsum("nohw,nchw->oc", dpre, xp[:, :, i:i + H, j:j + H], optimize=True)
+            dxp[:, :, i:i + H, j:j + H] += np.einsum("nohw,oc->nchw", dpre, w[:, i, j, :], optimize=True)
+    return gw, dpre.sum(axis=(0, 2, 3)), dxp[:, :, 1:-1, 1:-1], dpre
+
+
+def flatten(pooled):
+    """[N][128][4][4] -> [N][2048] in (h, w, c) order."""
+    return pooled.transpose(0, 2, 3, 1).reshape(pooled.shape[0], FLAT)
+
+
+def fc1(flat, w, b):
+    """Hidden layer h = ReLU(flat w^T + b)."""
+    return np.maximum(flat @ w.T + b, 0.0)
+
+
+def head_backward(z, y, h, w2):
+    """Loss head: mean BCE over the batch of z = h w2 + b2.  Returns
+    (dz = (sigmoid(z) - y) / n, dW2 = dz h, db2 = sum dz,
+    dh = dz w2 * [h > 0], the gradient of fc1's pre-activation)."""
+    n = z.shape[0]
+    dz = (1.0 / (1.0 + np.exp(-z)) - y) / n
+    return dz, dz @ h, np.array([dz.sum()]), np.outer(dz, w2) * (h > 0)
+
+
+def fc1_backward(dh, flat, w1):
+    """Given the gradient dh of fc1's pre-activation: (dW1 = dh^T flat,
+    db1 = sum_n dh, dflat = dh w1)."""
+    return dh.T @ flat, dh.sum(axis=0), dh @ w1
+
+
+def _params(params, quantized):
+    r = bf16 if quantized else (lambda a: a)
+    return {k: r(v) if k.endswith(".w") else v for k, v in unpack(params).items()}
+
+
+def forward(params, x, quantized=True):
+    """x: [N][2][64][64].  Returns (logits [N], cache)."""
+    P = _params(params, quantized)
+    a = bf16(np.asarray(x, dtype=np.float64)) if quantized else np.asarray(x, dtype=np.float64)
     cache = {"P": P, "in": [], "act": [], "q": []}
     for l in range(4):
         cache["in"].append(a)
-        act = r(np.maximum(conv3x3(a, P[f"conv{l + 1}.w"], P[f"conv{l + 1}.b"]), 0.0))
-        a, q = maxpool2(act)
+        act, a, q = conv_block(a, P[f"conv{l + 1}.w"], P[f"conv{l + 1}.b"])
         cache["act"].append(act)
         cache["q"].append(q)
     cache["pooled"] = a
-    flat = a.transpose(0, 2, 3, 1).reshape(a.shape[0], FLAT)  # (h, w, c) order
-    h = r(np.maximum(flat @ P["fc1.w"].T + P["fc1.b"], 0.0))
+    flat = flatten(a)
+    h = fc1(flat, P["fc1.w"], P["fc1.b"])
     z = h @ P["fc2.w"] + P["fc2.b"][0]
     cache.update(flat=flat, h=h, z=z)
     return z, cache
@@ -136,59 +195,31 @@ def bce(z, y):
     return np.maximum(z, 0.0) - z * y + np.log1p(np.exp(-np.abs(z)))
 
 
-def loss(params, x, y, exact=False):
-    z, _ = forward(params, x, exact)
+def loss(params, x, y, quantized=True):
+    z, _ = forward(params, x, quantized)
     return float(np.mean(bce(z, y)))
 
 
 def pattern(params, x):
-    """ReLU signs and pooling choices of the float64 forward pass (the loss is
-    smooth in the parameters while this stays the same)."""
-    _, c = forward(params, x, exact=True)
+    """ReLU signs and pooling choices of the unrounded forward pass (the loss
+    is smooth in the parameters while this stays the same)."""
+    _, c = forward(params, x, quantized=False)
     parts = [(a > 0).ravel() for a in c["act"]] + [q.ravel() for q in c["q"]] + [(c["h"] > 0).ravel()]
     return np.concatenate([p.astype(np.int64) for p in parts])
 
 
-def gradients(params, x, y, exact=False):
+def gradients(params, x, y, quantized=True):
     """Gradient of the mean loss with respect to the parameter vector; (grad, loss)."""
-    r = (lambda a: a) if exact else bf16
-    z, c = forward(params, x, exact)
+    z, c = forward(params, x, quantized)
     P = c["P"]
-    n = z.shape[0]
     y = np.asarray(y, dtype=np.float64)
     G = {}
-    dz = r((1.0 / (1.0 + np.exp(-z)) - y) / n)
-    G["fc2.w"] = dz @ c["h"]
-    G["fc2.b"] = np.array([dz.sum()])
-    dh = r(np.outer(dz, P["fc2.w"]) * (c["h"] > 0))
-    G["fc1.w"] = dh.T @ c["flat"]
-    G["fc1.b"] = dh.sum(axis=0)
-    dflat = r(dh @ P["fc1.w"])
-    dy = dflat.reshape(n, 4, 4, 128).transpose(0, 3, 1, 2)
+    _, G["fc2.w"], G["fc2.b"], dh = head_backward(z, y, c["h"], P["fc2.w"])
+    G["fc1.w"], G["fc1.b"], dflat = fc1_backward(dh, c["flat"], P["fc1.w"])
+    dy = dflat.reshape(-1, 4, 4, 128).transpose(0, 3, 1, 2)
     for l in range(3, -1, -1):
-        ci, co, H = CONV[l]
-        act, xin = c["act"][l], c["in"][l]
-        dpre = r(unpool2(dy, c["q"][l], H, H) * (act > 0))
-        xp = np.zeros((n, ci, H + 2, H + 2))
-        xp[:, :, 1:-1, 1:-1] = xin
-        gw = np.zeros((co, 3, 3, ci))
-        for i in range(3):
-            for j in range(3):
-                gw[:, i, j, :] = np.einsum("nohw,nchw->oc", dpre, xp[:, :, i:i + H, j:j + H], optimize=True)
-        G[f"conv{l + 1}.w"] = gw
-        G[f"conv{l + 1}.b"] = dpre.sum(axis=(0, 2, 3))
-        if l == 0:
-            break
-        # gradient of the input: each tap's contribution stored (bf16), then summed
-        w = P[f"conv{l + 1}.w"]
-        dxp = np.zeros((n, ci, H + 2, H + 2))
-        taps = np.zeros((n, ci, H + 2, H + 2))
-        for i in range(3):
-            for j in range(3):
-                taps[:] = 0.0
-                taps[:, :, i:i + H, j:j + H] = r(np.einsum("nohw,oc->nchw", dpre, w[:, i, j, :], optimize=True))
-                dxp += taps
-        dy = r(dxp[:, :, 1:-1, 1:-1])
+        G[f"conv{l + 1}.w"], G[f"conv{l + 1}.b"], dy, _ = conv_block_backward(
+            dy, c["in"][l], P[f"conv{l + 1}.w"], c["act"][l], c["q"][l])
     return pack(G), float(np.mean(bce(z, y)))
 
 

@@ -136,8 +136,8 @@ def test_forward_and_gradients_equal_torch_float64(net):
     max-pool the same way only without ties: random inputs have none)."""
     p, x, y = net
     zt, lt, gt = torch_reference(p, x, y)
-    z, _ = cnn.forward(p, x, exact=True)
-    g, l = cnn.gradients(p, x, y, exact=True)
+    z, _ = cnn.forward(p, x, quantized=False)
+    g, l = cnn.gradients(p, x, y, quantized=False)
     assert np.allclose(z, zt, rtol=1e-12, atol=1e-12)
     assert l == pytest.approx(lt, rel=1e-12)
     for name, sl in slices():
@@ -158,7 +158,7 @@ def test_gradients_equal_central_finite_differences(net):
     error <= 1e-6), with the ReLU / pooling pattern unchanged across the
     difference."""
     p, x, y = net
-    g, _ = cnn.gradients(p, x, y, exact=True)
+    g, _ = cnn.gradients(p, x, y, quantized=False)
     base = cnn.pattern(p, x)
     rng = np.random.default_rng(11)
     for name, sl in slices():
@@ -169,7 +169,7 @@ def test_gradients_equal_central_finite_differences(net):
             h = 1e-7 / np.sqrt(np.mean(v[sl] ** 2))
             if not ((cnn.pattern(p + h * v, x) == base).all() and (cnn.pattern(p - h * v, x) == base).all()):
                 continue
-            fd = (cnn.loss(p + h * v, x, y, exact=True) - cnn.loss(p - h * v, x, y, exact=True)) / (2 * h)
+            fd = (cnn.loss(p + h * v, x, y, quantized=False) - cnn.loss(p - h * v, x, y, quantized=False)) / (2 * h)
             an = float(g @ v)
             assert abs(fd - an) <= 1e-6 * abs(an) + 1e-12, (name, fd, an)
             done += 1
@@ -178,16 +178,78 @@ def test_gradients_equal_central_finite_differences(net):
         assert done >= 1, name
 
 
-def test_storage_rounding_changes_little(net):
-    """The bf16 storage mode stays within a few bf16 ulps (relative) of the
-    float64 network: a check that the rounding points do not break it."""
+def test_quantized_network_is_the_float64_network_on_bf16_values(net):
+    """quantized=True is the float64 network evaluated on the bf16-rounded
+    input and weights (biases stay as given), nothing else rounded: equal to
+    torch's float64 layers and autograd fed those rounded values, and a few
+    bf16 steps away from the unrounded network."""
     p, x, y = net
-    z0, _ = cnn.forward(p, x, exact=True)
-    z1, _ = cnn.forward(p, x, exact=False)
-    assert np.abs(z1 - z0).max() <= 0.05 * (np.abs(z0).max() + 1e-3)
-    g0, _ = cnn.gradients(p, x, y, exact=True)
-    g1, _ = cnn.gradients(p, x, y, exact=False)
-    assert np.linalg.norm(g1 - g0) <= 0.05 * np.linalg.norm(g0)
+    P = cnn.unpack(p)
+    pq = cnn.pack({k: cnn.bf16(v) if k.endswith(".w") else v for k, v in P.items()})
+    xq = cnn.bf16(x)
+    zt, lt, gt = torch_reference(pq, xq, y)
+    z, _ = cnn.forward(p, x, quantized=True)
+    g, l = cnn.gradients(p, x, y, quantized=True)
+    assert np.allclose(z, zt, rtol=1e-12, atol=1e-12)
+    assert l == pytest.approx(lt, rel=1e-12)
+    for name, sl in slices():
+        assert np.allclose(g[sl], gt[sl], rtol=1e-9, atol=1e-12 * np.abs(gt[sl]).max()), name
+    z0, _ = cnn.forward(p, x, quantized=False)
+    assert np.abs(z - z0).max() <= 0.05 * (np.abs(z0).max() + 1e-3)
+
+
+def test_layer_functions_compose_to_the_network(net):
+    """Feeding each layer function the previous one's output (forward) and
+    upstream gradient (backward) reproduces forward() and gradients()."""
+    p, x, y = net
+    P = cnn._params(p, True)
+    a = cnn.bf16(x)
+    ins, acts, qs = [], [], []
+    for l in range(4):
+        ins.append(a)
+        act, a, q = cnn.conv_block(a, P[f"conv{l + 1}.w"], P[f"conv{l + 1}.b"])
+        acts.append(act)
+        qs.append(q)
+    flat = cnn.flatten(a)
+    h = cnn.fc1(flat, P["fc1.w"], P["fc1.b"])
+    z = h @ P["fc2.w"] + P["fc2.b"][0]
+    zf, _ = cnn.forward(p, x)
+    assert np.array_equal(z, zf)
+    dz, gw2, gb2, dh = cnn.head_backward(z, y, h, P["fc2.w"])
+    gw1, gb1, dflat = cnn.fc1_backward(dh, flat, P["fc1.w"])
+    G = {"fc2.w": gw2, "fc2.b": gb2, "fc1.w": gw1, "fc1.b": gb1}
+    dy = dflat.reshape(-1, 4, 4, 128).transpose(0, 3, 1, 2)
+    for l in range(3, -1, -1):
+        G[f"conv{l + 1}.w"], G[f"conv{l + 1}.b"], dy, _ = cnn.conv_block_backward(
+            dy, ins[l], P[f"conv{l + 1}.w"], acts[l], qs[l])
+    g, _ = cnn.gradients(p, x, y)
+    assert np.array_equal(cnn.pack(G), g)
+    # dz closed form: sigmoid(z) - y over the batch
+    assert np.allclose(dz, (1 / (1 + np.exp(-z)) - y) / len(y), rtol=1e-15)
+
+
+def test_conv_block_input_gradient_is_the_transposed_convolution():
+    """dx of a block equals torch's float64 autograd of the block's output
+    against an arbitrary upstream gradient (the gradient the next layer
+    down receives)."""
+    import torch
+    import torch.nn.functional as F
+    rng = np.random.default_rng(13)
+    x = rng.normal(size=(2, 5, 8, 8))
+    w = rng.normal(size=(6, 3, 3, 5))
+    b = rng.normal(size=6)
+    act, pooled, q = cnn.conv_block(x, w, b)
+    dp = rng.normal(size=pooled.shape)
+    gw, gb, dx, _ = cnn.conv_block_backward(dp, x, w, act, q)
+    xt = torch.tensor(x, requires_grad=True)
+    wt = torch.tensor(w, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    out = F.max_pool2d(F.relu(F.conv2d(xt, wt.permute(0, 3, 1, 2), bt, padding=1)), 2)
+    assert np.allclose(out.detach().numpy(), pooled, rtol=1e-13)
+    out.backward(torch.tensor(dp))
+    assert np.allclose(dx, xt.grad.numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(gw, wt.grad.numpy(), rtol=1e-12, atol=1e-12)
+    assert np.allclose(gb, bt.grad.numpy(), rtol=1e-12, atol=1e-12)
 
 
 # --- cutouts -----------------------------------------------------------------
@@ -230,3 +292,32 @@ def test_cutout_padding_and_normalisation():
         assert abs(img[k].mean()) < 1e-12 and img[k].std() == pytest.approx(1.0, rel=1e-12)
     flat = cnn.cutout(np.full_like(row, 7), np.full(70, 7.0), np.full_like(Y, 3), delays, (20, 500, 8))
     assert (flat == 0).all()
+
+
+def test_cutout_frequency_time_edge_rule_hand_computed():
+    """A hand-computed case of the frequency-time edge rule: 64 channels, so
+    each band is one channel; box end e = 116 and width 16 give bins of
+    r = 2 samples starting at -11 + 2b.  Bin 5 covers samples -1 and 0 (one
+    valid sample, scaled to two), bins 0..4 lie wholly before the data and
+    take the mean of the band's 59 valid bins, bins 6..63 are plain sums of
+    the channel's samples shifted by its delay."""
+    nchan, N = 64, 300
+    Y = (np.arange(nchan)[:, None] * 1000 + np.arange(N)[None, :] * 3 + (np.arange(N)[None, :] % 7)).astype(np.int64)
+    delays = np.zeros((4, nchan), np.int64)
+    delays[2] = np.arange(nchan) % 5
+    row = np.zeros((4, N), np.int64)
+    mu = np.zeros(4)
+    raw = cnn.cutout(row, mu, Y, delays, (2, 101, 16), normalize=False)
+    for j in range(nchan):
+        d = int(delays[2, j])
+        want = np.zeros(64)
+        for b in range(6, 64):
+            t0 = -11 + 2 * b
+            want[b] = Y[j, t0 + d] + Y[j, t0 + 1 + d]
+        want[5] = 2 * Y[j, 0 + d]
+        want[:5] = want[5:].mean()
+        assert np.allclose(raw[1][j], want, rtol=0, atol=1e-9), j
+    # the same rule breaks visibly if the partial bin were left unscaled or
+    # the empty bins left at zero
+    assert raw[1][3][5] == 2 * Y[3, 3] and Y[3, 3] > 0
+    assert raw[1][3][:5].min() > 0
