@@ -367,6 +367,75 @@ def test_window_search_covers_series_when_whole():
     assert (a == b).all()
 
 
+def _brute_window(x, w0, w1, widths, thr, clip_at_window=False, stats_span=None):
+    """Pure-Python window search: statistics (population mean and sigma in
+    exact rationals) over x[w0:w1] (or over `stats_span`), every box end e in
+    [w0, w1), boxes [e-w+1, e] reaching back before w0 (or clipped at w0 when
+    asked, a deliberately wrong rule), best over the sorted width set (ties to
+    the smaller width), one candidate per maximal run at its argmax (ties to
+    the earlier end).  Returns [(t_peak, width, t_first, t_last, snr)]."""
+    a, b = stats_span if stats_span else (w0, w1)
+    seg = [int(v) for v in x[a:b]]
+    n = len(seg)
+    mean = Fraction(sum(seg), n)
+    var = Fraction(sum(v * v for v in seg), n) - mean * mean
+    mu, sg = float(mean), math.sqrt(float(var))
+    ws = sorted(set(widths))
+    best = []
+    for e in range(w0, w1):
+        bw, bs = 0, None
+        for w in ws:
+            lo = e - w + 1
+            if lo < 0 or (clip_at_window and lo < w0):
+                continue
+            snr = (sum(int(v) for v in x[lo:e + 1]) - w * mu) / (sg * math.sqrt(w))
+            if bs is None or snr > bs:
+                bw, bs = w, snr
+        best.append((e, bw, bs))
+    out, run = [], None
+    for e, bw, bs in best + [(w1, 0, None)]:
+        if bs is not None and bs >= thr:
+            if run is None:
+                run = [e, e, bw, bs, e]
+            else:
+                run[1] = e
+                if bs > run[3]:
+                    run[2], run[3], run[4] = bw, bs, e
+        elif run is not None:
+            first, last, bw_, bs_, ep = run
+            out.append((ep - bw_ + 1, bw_, first, last, bs_))
+            run = None
+    return out
+
+
+def test_window_search_reaches_back_and_takes_window_statistics():
+    """orc_search_window with w0 > 0 equals a brute-force loop: statistics
+    over [w0, w1) only, boxes ending in the window reaching back before w0,
+    runs cut at both window edges.  The case is built so that the two
+    plausible mistakes (boxes clipped at w0, statistics over the whole
+    series) give different candidates."""
+    rng = np.random.default_rng(4)
+    x = rng.normal(1000, 20, size=3000).round().astype(np.int32)
+    x[:1200] += 60                      # before the window: a different level
+    w0, w1 = 1200, 2400
+    x[1190:1203] += 120                 # a pulse straddling the window start
+    x[1700:1712] += 90                  # one inside
+    x[2395:2400] += 150                 # one touching the window end
+    widths = [1, 2, 4, 8, 16, 32]
+    thr = 6.0
+    got = oracle.search_window(x, w0, w1, widths, thr)
+    want = _brute_window(x, w0, w1, widths, thr)
+    assert len(got) == len(want) >= 3
+    for g, (tp, w, tf, tl, snr) in zip(got, want):
+        assert (g["t_peak"], g["width"], g["t_first"], g["t_last"]) == (tp, w, tf, tl)
+        assert g["snr"] == pytest.approx(snr, rel=1e-12)
+    assert want[0][0] < w0 and want[0][2] == w0       # its peak box starts before the window
+    assert want[-1][3] == w1 - 1                      # the last run is cut at the window end
+    # the wrong readings differ from the right one on this case
+    assert _brute_window(x, w0, w1, widths, thr, clip_at_window=True) != want
+    assert _brute_window(x, w0, w1, widths, thr, stats_span=(0, len(x))) != want
+
+
 # --- grouping ----------------------------------------------------------------
 
 def test_group_friends_of_friends():
