@@ -87,6 +87,15 @@ def lib():
         L.orc_search_window.restype = C.c_int64
         L.orc_search_window.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, P, C.c_int32, C.c_float,
                                         C.c_int32, P, C.c_int64]
+        L.orc_delay_ref.restype = C.c_int64
+        L.orc_delay_ref.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.orc_group_dm.restype = C.c_double
+        L.orc_group_dm.argtypes = [Seg, C.c_int32, C.c_int32]
+        L.orc_subband_delays.restype = None
+        L.orc_subband_delays.argtypes = [P, C.c_int32, C.c_int64, C.c_double, Seg, C.c_int32, C.c_int32, P, P]
+        L.orc_dedisperse_subband.restype = C.c_int
+        L.orc_dedisperse_subband.argtypes = [P, C.c_int64, C.c_int32, P, C.c_double, Seg, C.c_int32, C.c_int32,
+                                             C.c_int32, C.c_int32, C.c_int64, P]
         L.orc_group.restype = None
         L.orc_group.argtypes = [P, C.c_int64, P]
         _lib = L
@@ -179,6 +188,38 @@ def dedisperse_points(X: np.ndarray, freqs, tsamp: float, seg, trial, t) -> np.n
     out = np.empty(len(tr), np.int64)
     lib().orc_dedisperse_points(_ptr(X), nsamp, nchan, _ptr(f), tsamp, _seg(seg), _ptr(tr), _ptr(tt),
                                 len(tr), _ptr(out))
+    return out
+
+
+def group_dm(seg, group: int, g: int) -> float:
+    """Nominal DM of trial group g of a row in sub-band dedispersion."""
+    return float(lib().orc_group_dm(_seg(seg), int(group), int(g)))
+
+
+def subband_delays(freqs, nsamp: int, tsamp: float, seg, n_sub: int, group: int):
+    """(int64 [n_dm][nchan] composite delays d2(i, b(c)) + d1(g(i), c), n_out) of a row."""
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    d = np.empty((int(seg[2]), len(f)), np.int64)
+    n_out = C.c_int64()
+    lib().orc_subband_delays(_ptr(f), len(f), nsamp, tsamp, _seg(seg), int(n_sub), int(group), _ptr(d),
+                             C.byref(n_out))
+    return d, int(n_out.value)
+
+
+def dedisperse_subband(X: np.ndarray, freqs, tsamp: float, seg, n_sub: int, group: int, trials=None) -> np.ndarray:
+    """int32 [n_trials][n_out] of sub-band dedispersion, trials [i0, i1) of one row."""
+    X = np.ascontiguousarray(X, dtype=np.uint8)
+    nsamp, nchan = X.shape
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    _, n_out = subband_delays(f, nsamp, tsamp, seg, n_sub, group)
+    if n_out <= 0:
+        raise ValueError("input shorter than the row's largest composite delay")
+    i0, i1 = (0, int(seg[2])) if trials is None else trials
+    out = np.empty((i1 - i0, n_out), np.int32)
+    rc = lib().orc_dedisperse_subband(_ptr(X), nsamp, nchan, _ptr(f), tsamp, _seg(seg), int(n_sub), int(group), i0,
+                                      i1, n_out, _ptr(out))
+    if rc:
+        raise MemoryError("oracle allocation failed")
     return out
 
 

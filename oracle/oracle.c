@@ -290,6 +290,132 @@ int64_t orc_search_window(const int32_t *x, int64_t n, int64_t w0, int64_t w1, c
 }
 
 /*
+ * Sub-band (two-stage) dedispersion, the algorithm the paper's pipeline uses
+ * (Section 2.3 names it and cites Barsdell et al. 2012 for it; PRESTO's
+ * prepsubband works this way).  The channels are split into n_sub
+ * contiguous sub-bands, band b = channels [b*nchan/n_sub, (b+1)*nchan/n_sub),
+ * with reference frequency f_b = the band's highest channel frequency.  The
+ * row's trials are split into groups of `group` consecutive trials, group g
+ * = trials [g*group, min((g+1)*group, n_dm)), each with a nominal DM at its
+ * centre: DM_g = dm_lo + (g*group + (n_g - 1)/2) * dm_step, n_g its size.
+ *   stage 1: Z[g][b][t] = sum over channels c of band b of
+ *            Y[c][t + d1(g, c)],  d1(g, c) = delay of DM_g at f_c against f_b;
+ *   stage 2: out[i][t] = sum over bands b of Z[g(i)][b][t + d2(i, b)],
+ *            d2(i, b) = delay of DM_i at f_b against fref.
+ * Both delays use the rounding rule of orc_delay with the reference
+ * frequency replaced.  The valid length is n_out = floor(nsamp/D) - the
+ * largest d2(i, b) + max_{c in b} d1(g(i), c) over the row.  Composite
+ * delays differ from the brute-force ones by the in-band smearing of
+ * |DM_i - DM_g| plus at most one sample of double rounding.
+ */
+int64_t orc_delay_ref(double dm, double f, double fb, double tsamp, int32_t D) {
+  double r = ((ORC_K_DISP * dm) * (1.0 / (f * f) - 1.0 / (fb * fb))) / (tsamp * (double)D);
+  return (int64_t)floor(r + 0.5);
+}
+
+/* Highest frequency of the channels of band b. */
+static double orc_band_ref(const double *freqs, int32_t nchan, int32_t n_sub, int32_t b) {
+  int32_t c0 = (int32_t)((int64_t)b * nchan / n_sub), c1 = (int32_t)((int64_t)(b + 1) * nchan / n_sub);
+  double f = freqs[c0];
+  for (int32_t c = c0 + 1; c < c1; ++c)
+    if (freqs[c] > f) f = freqs[c];
+  return f;
+}
+
+/* Nominal DM of group g of a row. */
+double orc_group_dm(orc_seg s, int32_t group, int32_t g) {
+  int32_t first = g * group;
+  int32_t n_g = s.n_dm - first < group ? s.n_dm - first : group;
+  return s.dm_lo + ((double)first + (double)(n_g - 1) / 2.0) * s.dm_step;
+}
+
+/* Composite delay table int64 [n_dm][nchan]: d2(i, b(c)) + d1(g(i), c),
+ * and the row's valid length through *n_out. */
+void orc_subband_delays(const double *freqs, int32_t nchan, int64_t nsamp, double tsamp, orc_seg s, int32_t n_sub,
+                        int32_t group, int64_t *d, int64_t *n_out) {
+  double fref = orc_fref(freqs, nchan);
+  int64_t m = 0;
+  for (int32_t i = 0; i < s.n_dm; ++i) {
+    double dm = orc_trial_dm(s, i), dmg = orc_group_dm(s, group, i / group);
+    for (int32_t b = 0; b < n_sub; ++b) {
+      double fb = orc_band_ref(freqs, nchan, n_sub, b);
+      int64_t d2 = orc_delay_ref(dm, fb, fref, tsamp, s.downsamp);
+      int32_t c0 = (int32_t)((int64_t)b * nchan / n_sub), c1 = (int32_t)((int64_t)(b + 1) * nchan / n_sub);
+      int64_t m1 = 0;
+      for (int32_t c = c0; c < c1; ++c) {
+        int64_t d1 = orc_delay_ref(dmg, freqs[c], fb, tsamp, s.downsamp);
+        d[(int64_t)i * nchan + c] = d2 + d1;
+        if (d1 > m1) m1 = d1;
+      }
+      if (d2 + m1 > m) m = d2 + m1;
+    }
+  }
+  *n_out = nsamp / s.downsamp - m;
+}
+
+/*
+ * The two stages as written above, trials [i0, i1) of a row: stage 1 forms
+ * the sub-band series of every group the trials need over the samples
+ * stage 2 reads, stage 2 sums them.  out int32 [i1 - i0][n_out].
+ */
+int orc_dedisperse_subband(const uint8_t *X, int64_t nsamp, int32_t nchan, const double *freqs, double tsamp,
+                           orc_seg s, int32_t n_sub, int32_t group, int32_t i0, int32_t i1, int64_t n_out,
+                           int32_t *out) {
+  const int64_t D = s.downsamp, N = nsamp / s.downsamp;
+  double fref = orc_fref(freqs, nchan);
+  int32_t g0 = i0 / group, g1 = (i1 - 1) / group + 1;
+  int64_t *d1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)nchan);
+  int64_t *d2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_sub);
+  int64_t *Z = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_sub * (size_t)N);
+  if (!d1 || !d2 || !Z) {
+    free(d1);
+    free(d2);
+    free(Z);
+    return -1;
+  }
+  for (int32_t g = g0; g < g1; ++g) {
+    /* stage 1 for group g: every band, every sample whose channels all exist */
+    double dmg = orc_group_dm(s, group, g);
+    for (int32_t b = 0; b < n_sub; ++b) {
+      double fb = orc_band_ref(freqs, nchan, n_sub, b);
+      int32_t c0 = (int32_t)((int64_t)b * nchan / n_sub), c1 = (int32_t)((int64_t)(b + 1) * nchan / n_sub);
+      int64_t m1 = 0;
+      for (int32_t c = c0; c < c1; ++c) {
+        d1[c] = orc_delay_ref(dmg, freqs[c], fb, tsamp, s.downsamp);
+        if (d1[c] > m1) m1 = d1[c];
+      }
+#pragma omp parallel for schedule(static)
+      for (int64_t t = 0; t < N - m1; ++t) {
+        int64_t acc = 0;
+        for (int32_t c = c0; c < c1; ++c) {
+          int64_t j = t + d1[c];
+          for (int64_t k = 0; k < D; ++k) acc += X[(j * D + k) * nchan + c];
+        }
+        Z[(int64_t)b * N + t] = acc;
+      }
+    }
+    /* stage 2 for the group's trials in [i0, i1) */
+    int32_t ia = g * group > i0 ? g * group : i0;
+    int32_t ib = (g + 1) * group < i1 ? (g + 1) * group : i1;
+    for (int32_t i = ia; i < ib; ++i) {
+      double dm = orc_trial_dm(s, i);
+      for (int32_t b = 0; b < n_sub; ++b)
+        d2[b] = orc_delay_ref(dm, orc_band_ref(freqs, nchan, n_sub, b), fref, tsamp, s.downsamp);
+#pragma omp parallel for schedule(static)
+      for (int64_t t = 0; t < n_out; ++t) {
+        int64_t acc = 0;
+        for (int32_t b = 0; b < n_sub; ++b) acc += Z[(int64_t)b * N + t + d2[b]];
+        out[(int64_t)(i - i0) * n_out + t] = (int32_t)acc;
+      }
+    }
+  }
+  free(d1);
+  free(d2);
+  free(Z);
+  return 0;
+}
+
+/*
  * Friends-of-friends grouping of candidates of one segment.  Two candidates
  * are linked when their trial indices differ by at most one and their run
  * extents [t_first, t_last] overlap.  group[k] receives, for candidate k, the
