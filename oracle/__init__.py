@@ -96,6 +96,8 @@ def lib():
         L.orc_dedisperse_subband.restype = C.c_int
         L.orc_dedisperse_subband.argtypes = [P, C.c_int64, C.c_int32, P, C.c_double, Seg, C.c_int32, C.c_int32,
                                              C.c_int32, C.c_int32, C.c_int64, P]
+        L.orc_rfi_clean.restype = C.c_int64
+        L.orc_rfi_clean.argtypes = [P, C.c_int64, C.c_int32, C.c_double, C.c_int64, C.c_int32, P]
         L.orc_group.restype = None
         L.orc_group.argtypes = [P, C.c_int64, P]
         _lib = L
@@ -221,6 +223,16 @@ def dedisperse_subband(X: np.ndarray, freqs, tsamp: float, seg, n_sub: int, grou
     if rc:
         raise MemoryError("oracle allocation failed")
     return out
+
+
+def rfi_clean(X: np.ndarray, clip_sigma: float = 0.0, block: int = 2048, zero_dm: bool = False):
+    """(cleaned uint8 [nsamp][nchan], flagged spectra): clip of outlying
+    zero-DM spectra per block, then the zero-DM filter (oracle.c)."""
+    X = np.ascontiguousarray(X, dtype=np.uint8)
+    out = np.empty_like(X)
+    n = lib().orc_rfi_clean(_ptr(X), X.shape[0], X.shape[1], float(clip_sigma), int(block), int(bool(zero_dm)),
+                            _ptr(out))
+    return out, int(n)
 
 
 def stats(x: np.ndarray):
