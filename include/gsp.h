@@ -195,6 +195,7 @@ typedef struct gsp_stream_stats {
   int64_t blocks_pending;
   int64_t triage_scored, triage_rejected; /* candidates scored / dropped by the network */
   double triage_s;                        /* wall time of cutouts + network inside steps */
+  int64_t search_repeats;                 /* steps whose search ran again with a grown fragment buffer */
 } gsp_stream_stats;
 
 /* widths/threshold: the search of every beam (as gsp_single_pulse_search). */
@@ -245,6 +246,13 @@ int gsp_stream_snapshot(gsp_stream *s, int32_t beam_id, void *host_buf, int64_t 
 int gsp_stream_restore(gsp_stream *s, int32_t beam_id, const void *host_buf, int64_t bytes);
 /* 1 (default): replay the captured step graph; 0: launch the kernels directly. */
 int gsp_stream_set_graph(gsp_stream *s, int enable);
+/* Capacity of a step's buffer of run fragments (default 65,536; cap in
+ * [1, 2^30]).  A step whose search finds more grows the buffer and searches
+ * the same windows again before it returns (the windows are intact until the
+ * next step), so no candidate is lost; a smaller capacity only makes that
+ * happen sooner (tests).  Worker thread stopped; the next step captures
+ * its graph anew. */
+int gsp_stream_set_fragment_capacity(gsp_stream *s, int64_t cap);
 
 /* Launch shape of the dedispersion kernel for one plan row: each workgroup
  * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials
@@ -368,10 +376,20 @@ int gsp_cnn_gradients(gsp_cnn *cnn, const uint16_t *x_dev, const float *labels_d
  * call synchronises `stream`; without it the step stays asynchronous. */
 int gsp_cnn_train_step(gsp_cnn *cnn, const uint16_t *x_dev, const float *labels_dev, int64_t n, float lr,
                        float *loss_host, void *stream);
-/* Inspection of the last forward pass (tests): which = 0..3 the pooled
- * output of convolution block which+1, bf16 [n][h][w][c] (h = w = 32, 16, 8,
- * 4); 4 the hidden layer, bf16 [n][192]; 5 the logits, float [n].  `bytes`
- * must equal the size for the batch of the last pass.  Synchronises. */
+/* Inspection of stored tensors (tests), l = 0..3 the convolution block:
+ *   which = l       pooled output of block l, bf16 [n][h][w][c] (h = w = 32, 16, 8, 4);
+ *   which = 4       the hidden layer (after ReLU), bf16 [n][192];
+ *   which = 5       the logits, float [n];
+ *   which = 12 + l  ReLU output of block l before pooling, bf16 [n][2h][2h][c];
+ *   which = 16 + l  max-pool choice of block l, uint8 [n][h][w][c], 2*(row parity) + column parity;
+ * all of the last forward pass (gsp_cnn_forward, gsp_cnn_gradients or
+ * gsp_cnn_train_step), and, of the last backward pass (gsp_cnn_gradients or
+ * gsp_cnn_train_step, with no forward pass of another batch since):
+ *   which = 6 + l   gradient of the loss with respect to block l's pooled output, bf16 [n][h][w][c];
+ *   which = 10      gradient with respect to the hidden layer's pre-activation, bf16 [n][192];
+ *   which = 11      dloss/dlogit per sample, float [n].
+ * `bytes` must equal the size for that batch (GSP_EINVAL otherwise, and
+ * when no such pass has run).  Synchronises the device. */
 int gsp_cnn_activation(gsp_cnn *cnn, int32_t which, void *host_out, int64_t bytes);
 
 #ifdef __cplusplus

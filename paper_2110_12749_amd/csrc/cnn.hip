@@ -251,8 +251,10 @@ __global__ void k_im2col(const uint16_t *__restrict__ x, int64_t sn, int64_t sc,
   }
 }
 
-// dx(n, h, w, c) = sum over taps of dcol[pixel (h - dh, w - dw)][tap*C + c], NHWC bf16 output
-__global__ void k_col2im(const uint16_t *__restrict__ dcol, int N, int C, int H, int W, uint16_t *__restrict__ dx) {
+// dx(n, h, w, c) = sum over taps of dcol[pixel (h - dh, w - dw)][tap*C + c]:
+// the taps are fp32 products (the dcol GEMM keeps fp32), summed in fp32 and
+// rounded to bf16 once (NHWC output)
+__global__ void k_col2im(const float *__restrict__ dcol, int N, int C, int H, int W, uint16_t *__restrict__ dx) {
   const int64_t total = (int64_t)N * H * W * C;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(i % C);
@@ -263,7 +265,7 @@ __global__ void k_col2im(const uint16_t *__restrict__ dcol, int N, int C, int H,
     for (int tap = 0; tap < 9; ++tap) {
       const int hh = h - (tap / 3 - 1), ww = w - (tap % 3 - 1);
       if (hh < 0 || hh >= H || ww < 0 || ww >= W) continue;
-      s += bf2f(dcol[(((int64_t)n * H + hh) * W + ww) * 9 * C + tap * C + c]);
+      s += dcol[(((int64_t)n * H + hh) * W + ww) * 9 * C + tap * C + c];
     }
     dx[i] = f2bf(s);
   }
@@ -313,15 +315,43 @@ __global__ void k_pool_bwd(const uint16_t *__restrict__ dy, const uint8_t *__res
   }
 }
 
-// BCE with logits: per-sample loss and dz = (sigmoid(z) - y) / n (bf16 for the GEMMs)
-__global__ void k_bce(const float *__restrict__ z, const float *__restrict__ y, int n, float *__restrict__ loss,
-                      uint16_t *__restrict__ dz) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float zi = z[i], yi = y[i];
-  loss[i] = fmaxf(zi, 0.f) - zi * yi + log1pf(expf(-fabsf(zi)));
-  const float s = 1.f / (1.f + expf(-zi));
-  dz[i] = f2bf((s - yi) / (float)n);
+static constexpr int kHiddenUnits = 192;  // fc1 outputs
+
+// Loss head, per (sample i, hidden unit j): BCE with logits, dz_i =
+// (sigmoid(z_i) - y_i) / n kept in fp32, and the gradient of fc1's
+// pre-activation dh[i][j] = dz_i * w2[j] * [h[i][j] > 0] rounded to bf16 once
+// (w2 the bf16 weights the forward pass used).  Lane j = 0 also stores the
+// sample's loss and dz.
+__global__ void k_head_bwd(const float *__restrict__ z, const float *__restrict__ y, const uint16_t *__restrict__ h,
+                           const uint16_t *__restrict__ w2, int n, float *__restrict__ loss,
+                           float *__restrict__ dz, uint16_t *__restrict__ dh) {
+  const int64_t total = (int64_t)n * kHiddenUnits;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(k / kHiddenUnits), j = (int)(k - (int64_t)i * kHiddenUnits);
+    const float zi = z[i], yi = y[i];
+    const float g = (1.f / (1.f + expf(-zi)) - yi) / (float)n;
+    if (j == 0) {
+      loss[i] = fmaxf(zi, 0.f) - zi * yi + log1pf(expf(-fabsf(zi)));
+      dz[i] = g;
+    }
+    dh[k] = f2bf(bf2f(h[k]) > 0.f ? g * bf2f(w2[j]) : 0.f);
+  }
+}
+
+// fc2's parameter gradients from the fp32 dz: dW2[j] = sum_i dz_i h[i][j]
+// (threads j < 192), db2 = sum_i dz_i (thread 192); one workgroup.
+__global__ __launch_bounds__(256) void k_head_wgrad(const float *__restrict__ dz, const uint16_t *__restrict__ h,
+                                                    int n, float *__restrict__ dw2, float *__restrict__ db2) {
+  const int j = threadIdx.x;
+  if (j > kHiddenUnits) return;
+  float s = 0.f;
+  if (j < kHiddenUnits) {
+    for (int i = 0; i < n; ++i) s += dz[i] * bf2f(h[(int64_t)i * kHiddenUnits + j]);
+    dw2[j] = s;
+  } else {
+    for (int i = 0; i < n; ++i) s += dz[i];
+    *db2 = s;
+  }
 }
 
 // Adam on fp32 master parameters; refreshes the bf16 copy
@@ -817,7 +847,7 @@ struct ConvSpec {
   int cin, cout, h;  // input channels, output channels, input height = width
 };
 static const ConvSpec kConv[4] = {{2, 16, 64}, {16, 32, 32}, {32, 64, 16}, {64, 128, 8}};
-static constexpr int kFlat = 128 * 4 * 4, kHidden = 192;
+static constexpr int kFlat = 128 * 4 * 4, kHidden = kHiddenUnits;
 
 struct ParamLayout {
   int64_t w[6], b[6];  // offsets (conv1..4, fc1, fc2)
@@ -863,7 +893,9 @@ struct gsp_cnn {
   // activations and scratch for batches up to `cap`
   int64_t cap = 0;
   int64_t last_n = 0;  // batch of the last forward pass
-  DevBuf col[4], act[4], pool[4], idx[4], h1, z, dz, loss, dh1, dp4, dcol, dpre, dpool;
+  DevBuf col[4], act[4], pool[4], idx[4], h1, z, dz, loss, dh1, dcol, dpre;
+  DevBuf dpool[4];        // gradient of each block's pooled output (bf16, NHWC)
+  int64_t last_bwd_n = 0;  // batch of the last backward pass
 };
 
 namespace {
@@ -884,17 +916,19 @@ void reserve_batch(gsp_cnn *c, int64_t n) {
   }
   int64_t big = 0;
   for (int l = 0; l < 4; ++l) big = std::max<int64_t>(big, n * kConv[l].h * kConv[l].h * 9 * kConv[l].cin);
-  for (DevBuf *d : {&c->h1, &c->z, &c->dz, &c->loss, &c->dh1, &c->dp4, &c->dcol, &c->dpre, &c->dpool, &c->ones})
-    d->device = dev;
+  for (DevBuf *d : {&c->h1, &c->z, &c->dz, &c->loss, &c->dh1, &c->dcol, &c->dpre, &c->ones}) d->device = dev;
   c->h1.reserve((size_t)n * kHidden * 2);
   c->z.reserve((size_t)n * 4);
-  c->dz.reserve((size_t)n * 2);
+  c->dz.reserve((size_t)n * 4);
   c->loss.reserve((size_t)n * 4);
   c->dh1.reserve((size_t)n * kHidden * 2);
-  c->dp4.reserve((size_t)n * kFlat * 2);
-  c->dcol.reserve((size_t)big * 2);
+  c->dcol.reserve((size_t)big * 4);  // fp32 taps
   c->dpre.reserve((size_t)n * 64 * 64 * 16 * 2);
-  c->dpool.reserve((size_t)n * 32 * 32 * 16 * 2);
+  for (int l = 0; l < 4; ++l) {
+    const int h = kConv[l].h / 2;
+    c->dpool[l].device = dev;
+    c->dpool[l].reserve((size_t)n * h * h * kConv[l].cout * 2);
+  }
   c->ones.reserve((size_t)n * 64 * 64 * 2);
   hipLaunchKernelGGL(k_fill_bf16, dim3(grid_for(n * 4096)), dim3(256), 0, 0, c->ones.as<uint16_t>(), n * 4096,
                      (uint16_t)0x3F80);
@@ -976,24 +1010,20 @@ void backward(gsp_cnn *c, const float *labels, int64_t n, hipStream_t st) {
   const uint16_t *wb = c->pbf.as<uint16_t>();
   float *g = c->g32.as<float>();
   const uint16_t *ones = c->ones.as<uint16_t>();
-  hipLaunchKernelGGL(k_bce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->z.as<float>(), labels, (int)n,
-                     c->loss.as<float>(), c->dz.as<uint16_t>());
-  const uint16_t *dz = c->dz.as<uint16_t>();
-  // fc2: dW = dz^T h1, db = sum dz, dh1 = dz W2 masked by ReLU
-  gemm(ga(dz, 0, 1, c->h1.as<uint16_t>(), kHidden, 1, g + c->L.w[5], 1, 1, 1, kHidden, n), st);
-  gemm(ga(ones, 0, 0, dz, 1, 0, g + c->L.b[5], 1, 1, 1, 1, n), st);
-  GemmArgs gh = ga(dz, 1, 0, wb + c->L.w[5], 0, 1, c->dh1.ptr, kHidden, 1, n, kHidden, 1);
-  gh.mask = c->h1.as<uint16_t>();
-  gh.out_bf16 = 1;
-  gemm(gh, st);
+  // loss head: fp32 dz, fc2's gradients from it, bf16 gradient of fc1's pre-activation
+  hipLaunchKernelGGL(k_head_bwd, dim3(grid_for(n * kHidden)), dim3(256), 0, st, c->z.as<float>(), labels,
+                     c->h1.as<uint16_t>(), wb + c->L.w[5], (int)n, c->loss.as<float>(), c->dz.as<float>(),
+                     c->dh1.as<uint16_t>());
+  hipLaunchKernelGGL(k_head_wgrad, dim3(1), dim3(256), 0, st, c->dz.as<float>(), c->h1.as<uint16_t>(), (int)n,
+                     g + c->L.w[5], g + c->L.b[5]);
   const uint16_t *dh = c->dh1.as<uint16_t>();
   // fc1: dW = dh^T x, db = colsum dh, dx = dh W1
   gemm(ga(dh, 1, kHidden, c->pool[3].as<uint16_t>(), kFlat, 1, g + c->L.w[4], kFlat, 1, kHidden, kFlat, n), st);
   gemm(ga(ones, 0, 0, dh, kHidden, 1, g + c->L.b[4], 1, 1, 1, kHidden, n), st);
-  GemmArgs gx = ga(dh, kHidden, 1, wb + c->L.w[4], kFlat, 1, c->dp4.ptr, kFlat, 1, n, kFlat, kHidden);
+  GemmArgs gx = ga(dh, kHidden, 1, wb + c->L.w[4], kFlat, 1, c->dpool[3].ptr, kFlat, 1, n, kFlat, kHidden);
   gx.out_bf16 = 1;
   gemm(gx, st);
-  const uint16_t *dy = c->dp4.as<uint16_t>();  // gradient of the pooled output of conv l
+  const uint16_t *dy = c->dpool[3].as<uint16_t>();  // gradient of the pooled output of conv l
   for (int l = 3; l >= 0; --l) {
     const ConvSpec &cs = kConv[l];
     const int H = cs.h;
@@ -1005,15 +1035,14 @@ void backward(gsp_cnn *c, const float *labels, int64_t n, hipStream_t st) {
     gemm(ga(dpre, 1, cs.cout, c->col[l].as<uint16_t>(), K, 1, g + c->L.w[l], K, 1, cs.cout, K, M), st);
     gemm(ga(ones, 0, 0, dpre, cs.cout, 1, g + c->L.b[l], 1, 1, 1, cs.cout, M), st);
     if (l == 0) break;
-    // dcol = dpre W; dx = col2im(dcol) (NHWC of the previous pooled output)
+    // dcol = dpre W (fp32); dx = col2im(dcol) (NHWC of the previous pooled output)
     GemmArgs gc = ga(dpre, cs.cout, 1, wb + c->L.w[l], K, 1, c->dcol.ptr, K, 1, M, K, cs.cout);
-    gc.out_bf16 = 1;
     gemm(gc, st);
-    hipLaunchKernelGGL(k_col2im, dim3(grid_for(M * cs.cin)), dim3(256), 0, st, c->dcol.as<uint16_t>(), (int)n, cs.cin,
-                       H, H, c->dpool.as<uint16_t>());
-    // the dpool buffer is consumed by the next layer's pool_bwd before being rewritten
-    dy = c->dpool.as<uint16_t>();
+    hipLaunchKernelGGL(k_col2im, dim3(grid_for(M * cs.cin)), dim3(256), 0, st, c->dcol.as<float>(), (int)n, cs.cin,
+                       H, H, c->dpool[l - 1].as<uint16_t>());
+    dy = c->dpool[l - 1].as<uint16_t>();
   }
+  c->last_bwd_n = n;
 }
 
 uint64_t splitmix64(uint64_t &s) {
@@ -1185,20 +1214,43 @@ int gsp_cnn_train_step(gsp_cnn *c, const uint16_t *x, const float *labels, int64
 int gsp_cnn_activation(gsp_cnn *c, int32_t which, void *host, int64_t bytes) {
   if (!c) return GSP_EINVAL;
   return guarded(c->ctx, [&] {
-    const int64_t n = c->last_n;
-    if (!host || which < 0 || which > 5 || n < 1) fail(GSP_EINVAL, "bad arguments or no forward pass yet");
+    if (!host || which < 0 || which > 19) fail(GSP_EINVAL, "bad arguments");
+    const bool bwd = which >= 6 && which <= 11;
+    const int64_t n = bwd ? c->last_bwd_n : c->last_n;
+    if (n < 1) fail(GSP_EINVAL, bwd ? "no backward pass yet" : "no forward pass yet");
+    if (bwd && c->last_n != c->last_bwd_n) fail(GSP_EINVAL, "a forward pass of another batch followed the backward pass");
     const void *src;
     int64_t want;
-    if (which < 4) {
+    if (which < 4) {  // pooled output of block which
       const int h = kConv[which].h / 2;
       want = n * h * h * kConv[which].cout * 2;
       src = c->pool[which].ptr;
     } else if (which == 4) {
       want = n * kHidden * 2;
       src = c->h1.ptr;
-    } else {
+    } else if (which == 5) {
       want = n * 4;
       src = c->z.ptr;
+    } else if (which < 10) {  // gradient of the pooled output of block which - 6
+      const int l = which - 6;
+      const int h = kConv[l].h / 2;
+      want = n * h * h * kConv[l].cout * 2;
+      src = c->dpool[l].ptr;
+    } else if (which == 10) {
+      want = n * kHidden * 2;
+      src = c->dh1.ptr;
+    } else if (which == 11) {
+      want = n * 4;
+      src = c->dz.ptr;
+    } else if (which < 16) {  // ReLU output of block which - 12, before pooling
+      const int l = which - 12;
+      want = n * kConv[l].h * kConv[l].h * kConv[l].cout * 2;
+      src = c->act[l].ptr;
+    } else {  // max-pool choices of block which - 16
+      const int l = which - 16;
+      const int h = kConv[l].h / 2;
+      want = n * h * h * kConv[l].cout;
+      src = c->idx[l].ptr;
     }
     if (bytes != want) fail(GSP_EINVAL, "size does not match the last batch");
     check_hip(hipDeviceSynchronize(), "synchronise");

@@ -341,6 +341,7 @@ struct gsp_stream {
   std::unique_ptr<SeriesTable> h_series = std::make_unique<SeriesTable>();
   std::unique_ptr<TailTable> h_tail = std::make_unique<TailTable>();
   int64_t frag_cap = 1 << 16;
+  int64_t regrown = 0;  // steps whose search ran again with a grown fragment buffer
   int64_t musig_cap = 0;
   // graph
   hipGraph_t graph = nullptr;
@@ -507,9 +508,12 @@ int64_t step_once(gsp_stream *s) {
   std::vector<Work> work;
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    int64_t rows = 0;  // one staging, dedispersion, series and shift job per (beam, row) at most
     for (auto &kv : s->beams) {
       Beam &b = *kv.second;
       if (b.admitted && !b.pending.empty()) {
+        if (rows + (int64_t)b.rows.size() > kMaxJobs) break;  // the rest wait for the next step
+        rows += (int64_t)b.rows.size();
         work.push_back({&b, b.pending.front()});
         b.pending.pop_front();
         b.inflight = true;
@@ -696,8 +700,26 @@ int64_t step_once(gsp_stream *s) {
   unsigned long long count = 0;
   check_hip(hipMemcpyAsync(&count, s->counter.ptr, sizeof(count), hipMemcpyDeviceToHost, st), "copy count");
   check_hip(hipStreamSynchronize(st), "synchronise stream");
-  if ((int64_t)count > s->frag_cap)
-    fail(GSP_ECAPACITY, "more run fragments in one step than the stream's capacity");
+  if ((int64_t)count > s->frag_cap) {
+    // Until the next step's look-back shift the window buffers and the
+    // statistics of this step stay as they are: grow the fragment buffer and
+    // search the same windows again, outside the graph (whose captured
+    // buffer pointer is now stale, so the next step captures anew).
+    s->frag_cap = ((int64_t)count + (int64_t)count / 4 + 4095) / 4096 * 4096;
+    s->frags.reserve((size_t)s->frag_cap * sizeof(Frag));
+    if (s->exec) {
+      (void)hipGraphExecDestroy(s->exec);
+      s->exec = nullptr;
+    }
+    set_search_attributes(s->tiling);
+    launch_search_table(nullptr, s->d_series.as<SeriesTable>(), grid_of(4), s->tiling, s->musig.as<double>(),
+                        s->d_widths.as<int32_t>(), (int32_t)s->widths.size(), s->wmax, s->thr, s->frags.as<Frag>(),
+                        s->frag_cap, s->counter.as<unsigned long long>(), 0, st);
+    check_hip(hipMemcpyAsync(&count, s->counter.ptr, sizeof(count), hipMemcpyDeviceToHost, st), "copy count");
+    check_hip(hipStreamSynchronize(st), "synchronise stream");
+    s->regrown += 1;
+    if ((int64_t)count > s->frag_cap) fail(GSP_EDEVICE, "the repeated search found more fragments");
+  }
   std::vector<Frag> fr(count);
   if (count)
     check_hip(hipMemcpy(fr.data(), s->frags.ptr, count * sizeof(Frag), hipMemcpyDeviceToHost), "copy fragments");
@@ -936,14 +958,20 @@ int gsp_stream_push(gsp_stream *s, int32_t beam_id, const uint8_t *block, int64_
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->beams.find(beam_id);
     if (it == s->beams.end()) fail(GSP_EINVAL, "unknown beam");
-    Beam &b = *it->second;
-    if (b.ended || b.closing) fail(GSP_EINVAL, "beam already ended");
-    const size_t bytes = (size_t)s->B * b.nchan;
+    if (it->second->ended || it->second->closing) fail(GSP_EINVAL, "beam already ended");
+    const int32_t nchan = it->second->nchan;
+    const size_t bytes = (size_t)s->B * nchan;
     PendingBlock p;
     p.buf = take_pinned(s, bytes);
-    lk.unlock();
-    std::memcpy(p.buf.p, block, (size_t)nsamp * b.nchan);
+    lk.unlock();  // the copy runs unlocked; the beam may be closed meanwhile
+    std::memcpy(p.buf.p, block, (size_t)nsamp * nchan);
     lk.lock();
+    it = s->beams.find(beam_id);
+    if (it == s->beams.end() || it->second->ended || it->second->closing) {
+      give_pinned(s, p.buf);
+      fail(GSP_EINVAL, "beam closed while its block was being copied");
+    }
+    Beam &b = *it->second;
     p.nsamp = nsamp;
     p.arrival = Clock::now();
     if (nsamp < s->B) b.ended = true;
@@ -994,11 +1022,19 @@ int gsp_stream_start(gsp_stream *s) {
           });
           if (s->stop) break;
         }
+        std::string err;
         try {
           step_once(s);
         } catch (const Error &e) {
+          err = e.msg;
+        } catch (const std::bad_alloc &) {
+          err = "host allocation failed";
+        } catch (...) {
+          err = "unexpected internal error";
+        }
+        if (!err.empty()) {
           std::lock_guard<std::mutex> lk(s->mu);
-          s->last_error = e.msg;
+          s->last_error = err;
           s->stop = true;
           s->cv.notify_all();
           break;
@@ -1084,6 +1120,7 @@ int gsp_stream_report(gsp_stream *s, gsp_stream_stats *r) {
     r->triage_scored = s->scored;
     r->triage_rejected = s->rejected;
     r->triage_s = s->triage_s;
+    r->search_repeats = s->regrown;
     for (auto &kv : s->beams) {
       if (kv.second->admitted)
         r->beams_active += 1;
@@ -1192,6 +1229,20 @@ int gsp_stream_restore(gsp_stream *s, int32_t beam_id, const void *host_buf, int
 
 int gsp_stream_set_graph(gsp_stream *s, int enable) {
   return sguard(s, [&] { s->use_graph = enable != 0; });
+}
+
+int gsp_stream_set_fragment_capacity(gsp_stream *s, int64_t cap) {
+  return sguard(s, [&] {
+    if (s->running) fail(GSP_EINVAL, "the stream's worker thread is running");
+    if (cap < 1 || cap > (int64_t(1) << 30)) fail(GSP_EINVAL, "capacity must be in [1, 2^30]");
+    check_hip(hipStreamSynchronize(s->st), "synchronise stream");
+    s->frag_cap = cap;
+    s->frags.reserve((size_t)cap * sizeof(Frag));
+    if (s->exec) {  // the captured buffer pointer may have changed
+      (void)hipGraphExecDestroy(s->exec);
+      s->exec = nullptr;
+    }
+  });
 }
 
 }  // extern "C"

@@ -303,7 +303,7 @@ class StreamStats(C.Structure):
                 ("blocks", C.c_int64), ("steps", C.c_int64), ("busy_s", C.c_double), ("mem_used", C.c_int64),
                 ("mem_budget", C.c_int64), ("beams_active", C.c_int32), ("beams_queued", C.c_int32),
                 ("blocks_pending", C.c_int64), ("triage_scored", C.c_int64), ("triage_rejected", C.c_int64),
-                ("triage_s", C.c_double)]
+                ("triage_s", C.c_double), ("search_repeats", C.c_int64)]
 
 
 STREAM_CAND_DTYPE = np.dtype([("beam", np.int32), ("block", np.int32)] + [(n, CAND_DTYPE[n]) for n in CAND_DTYPE.names]
@@ -339,6 +339,8 @@ _L.gsp_stream_restore.restype = C.c_int
 _L.gsp_stream_restore.argtypes = [P, C.c_int32, P, C.c_int64]
 _L.gsp_stream_set_graph.restype = C.c_int
 _L.gsp_stream_set_graph.argtypes = [P, C.c_int]
+_L.gsp_stream_set_fragment_capacity.restype = C.c_int
+_L.gsp_stream_set_fragment_capacity.argtypes = [P, C.c_int64]
 _L.gsp_stream_set_triage.restype = C.c_int
 _L.gsp_stream_set_triage.argtypes = [P, P, C.c_float]
 
@@ -407,6 +409,9 @@ class Stream:
 
     def set_graph(self, on: bool):
         self._check(_L.gsp_stream_set_graph(self.h, int(bool(on))))
+
+    def set_fragment_capacity(self, cap: int):
+        self._check(_L.gsp_stream_set_fragment_capacity(self.h, int(cap)))
 
     def set_triage(self, cnn, threshold: float = 0.0):
         """Attach a trained Cnn (None: the plain search) scoring each step's candidates."""
@@ -572,15 +577,27 @@ class Cnn:
         return float(loss.value) if want_loss else None
 
     def activation(self, which: int, n: int) -> np.ndarray:
-        """Stored activation of the last forward pass (bf16 values as float64
-        for which < 5, float32 logits for 5)."""
-        if which < 4:
-            h = 32 >> which
-            shape, dt = (n, h, h, 16 << which), np.uint16
-        elif which == 4:
+        """A stored tensor of the last forward / backward pass (the header's
+        table of `which`): bf16 values as float64, float32 logits and
+        dloss/dlogit, uint8 max-pool choices."""
+        if which < 4 or 6 <= which < 10:
+            l = which % 6
+            h = 32 >> l
+            shape, dt = (n, h, h, 16 << l), np.uint16
+        elif which in (4, 10):
             shape, dt = (n, 192), np.uint16
-        else:
+        elif which in (5, 11):
             shape, dt = (n,), np.float32
+        elif 12 <= which < 16:
+            l = which - 12
+            h = 64 >> l
+            shape, dt = (n, h, h, 16 << l), np.uint16
+        elif 16 <= which < 20:
+            l = which - 16
+            h = 32 >> l
+            shape, dt = (n, h, h, 16 << l), np.uint8
+        else:
+            raise ValueError(which)
         out = np.empty(shape, dt)
         _check(_L.gsp_cnn_activation(self.h, int(which), out.ctypes.data, out.nbytes), self.ctx.h)
         if dt == np.uint16:

@@ -89,24 +89,35 @@ class Beam:
         self.fb = self.dmt = None
 
 
-def pick_candidates(b: Beam, per_event: int, per_pulse: int, rng) -> np.ndarray:
+def pick_candidates(b: Beam, per_event: int, per_pulse: int, rng, neg_per_pos: float | None = None) -> np.ndarray:
     """Training candidates of a beam: every event's representative plus up
     to per_event - 1 other members, with the candidates matched to any one
     injected pulse capped at per_pulse (a bright pulse yields thousands of
     near-identical candidates, a faint one a handful; the cap keeps the
-    faint ones from being outweighed)."""
+    faint ones from being outweighed).  With neg_per_pos, the unmatched
+    candidates are subsampled to at most that many per matched one (plus
+    256), before anything is cut out."""
     pick = []
-    for e in b.events():
-        members = np.flatnonzero(b.rep == b.rep[e])
+    order = np.argsort(b.rep, kind="stable")
+    for members in np.split(order, np.flatnonzero(np.diff(b.rep[order])) + 1):
+        if not len(members):
+            continue
+        e = int(b.rep[members[0]])  # the event's representative
         others = members[members != e]
         extra = rng.choice(others, size=min(len(others), per_event - 1), replace=False) if len(others) else []
         pick.extend([e, *extra])
     pick = np.unique(np.asarray(pick, np.int64))
     pos = b.pulse[pick]
-    keep = [pick[pos < 0]]
+    keep = []
+    n_pos = 0
     for k in np.unique(pos[pos >= 0]):
         mine = pick[pos == k]
         keep.append(rng.choice(mine, size=min(len(mine), per_pulse), replace=False))
+        n_pos += len(keep[-1])
+    neg = pick[pos < 0]
+    if neg_per_pos is not None:
+        neg = rng.choice(neg, size=min(len(neg), int(neg_per_pos * n_pos) + 256), replace=False)
+    keep.append(neg)
     return np.sort(np.concatenate(keep))
 
 
@@ -169,7 +180,9 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--margin", type=float, default=0.5, help="logit margin below the weakest validation pulse")
+    ap.add_argument("--margin", type=float, default=2.0, help="logit margin below the weakest validation pulse")
+    ap.add_argument("--neg-per-pos", type=float, default=3.0,
+                    help="unmatched training candidates cut out per matched one (plus 256) in each beam")
     ap.add_argument("--save", default=None, help="write the trained parameters here")
     args = ap.parse_args()
     import torch
@@ -180,7 +193,7 @@ def main():
     xs, ys = [], []
     for k in range(args.train_beams):
         b = Beam(ctx, synth.triage_beam(k, "train"), torch)
-        pick = pick_candidates(b, args.per_event, args.per_pulse, rng)
+        pick = pick_candidates(b, args.per_event, args.per_pulse, rng, args.neg_per_pos)
         if len(pick):
             xs.append(gsp.cutouts(ctx, b.fb, b.w.freqs, b.dmt, b.desc, b.cands[pick]))
             ys.append((b.pulse[pick] >= 0).astype(np.float32))

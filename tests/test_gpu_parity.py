@@ -106,53 +106,71 @@ def test_saturated_input_no_overflow(env):
     assert len(ctx.single_pulse_search(dmt, desc, [1, 2, 4], 3.0)) == 0
 
 
-def _full_size_sampled(env, w):
-    """Sampled outputs of every row bit-exact (corners + 300 random points
-    per row), and whole-row searches of selected trials (the trials of 3
-    injected pulses and a low-DM trial) matched against the oracle."""
+@pytest.fixture(scope="module")
+def full_cache(env):
+    """One full-size workload at a time: (workload, input, plan, DM-time array
+    on the device, the search's candidates)."""
     gsp, ctx, torch = env
-    say(f"[case] {w.name} full size: generate")
-    X, desc, dmt = _run(env, w)
-    say(f"[case] {w.name}: sampled points")
-    rng = np.random.default_rng(1)
-    views = gsp.segment_views(desc, dmt)
-    for s, seg in enumerate(w.segments):
-        n_dm, n_out = seg[2], desc.n_out[s]
-        tr = np.concatenate([[0, n_dm - 1, 0, n_dm - 1], rng.integers(0, n_dm, 300)])
-        tt = np.concatenate([[0, 0, n_out - 1, n_out - 1], rng.integers(0, n_out, 300)])
-        ref = oracle.dedisperse_points(X, w.freqs, w.tsamp, seg, tr, tt)
-        got = views[s][torch.from_numpy(tr).long().cuda(), torch.from_numpy(tt).long().cuda()].cpu().numpy()
-        assert (got.astype(np.int64) == ref).all(), f"row {s}"
-    say(f"[case] {w.name}: search of selected trials")
-    cg = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold)
-    # the trial closest to each of 3 pulses, plus a low-DM trial
-    picks = []
-    for p in w.pulses[:3]:
-        for s, (lo, st, n, D) in enumerate(w.segments):
-            i = int(round((p.dm - lo) / st))
-            if 0 <= i < n:
-                picks.append((s, i))
-                break
-    picks.append((0, 3))
-    for s, i in picks:
-        say(f"  oracle row {s} trial {i}")
-        row = oracle.dedisperse_segment(X, w.freqs, w.tsamp, w.segments[s], trials=(i, i + 1))
-        co = oracle_cands_with_seg([(s, oracle.search_series(row[0], w.widths, w.threshold, trial=i))])
-        sel = cg[(cg["seg"] == s) & (cg["dm_index"] == i)]
-        match_candidates(sel, co, w.threshold)
-        say(f"  row {s} trial {i}: gpu {len(sel)} oracle {len(co)}")
-    del dmt
+    cache = {}
+    yield cache
+    cache.clear()
     torch.cuda.empty_cache()
 
 
-def test_realistic_full_size_sampled(env):
+def _full(env, cache, name):
+    gsp, ctx, torch = env
+    if name not in cache:
+        cache.clear()
+        torch.cuda.empty_cache()
+        w = getattr(synth, name)()
+        say(f"[case] {name} full size: generate, dedisperse, search")
+        X, desc, dmt = _run(env, w)
+        cg = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold)
+        cache[name] = (w, X, desc, dmt, cg)
+    return cache[name]
+
+
+def parity_trials(n_dm):
+    """The first, the last and every 37th trial of a plan row."""
+    return sorted(set([0, n_dm - 1] + list(range(0, n_dm, 37))))
+
+
+FULL_ROWS = [("realistic", r) for r in range(4)] + [("wideband", r) for r in range(4)]
+
+
+@pytest.mark.parametrize("name,row", FULL_ROWS, ids=[f"{n}-row{r}" for n, r in FULL_ROWS])
+def test_full_size_rows_parity(env, full_cache, name, row):
     """The realistic workload (4096 ch over 1000-1500 MHz, 2^20 samples, 3850
-    trials in 4 rows) at full size."""
-    _full_size_sampled(env, synth.realistic())
-
-
-def test_wideband_full_size_sampled(env):
-    """The wideband large-delay workload (4096 ch over 270-1620 MHz, 2^19
-    samples, 3350 trials, maximum delay 84,250 samples at D = 4, RFI bursts
-    and zero-DM spikes) at full size."""
-    _full_size_sampled(env, synth.wideband())
+    trials in 4 rows) and the wideband large-delay workload (4096 ch over
+    270-1620 MHz, 2^19 samples, 3350 trials, maximum delay 84,250 samples at
+    D = 4, RFI bursts and zero-DM spikes) at full size: whole dedispersed
+    series of the first, the last and every 37th trial of the row, and of the
+    trials nearest the injected pulses, bit-exact against the oracle, the search's candidates of those trials matched
+    against the oracle's search of its own series, and corners plus 300
+    random outputs of the row bit-exact."""
+    gsp, ctx, torch = env
+    w, X, desc, dmt, cg = _full(env, full_cache, name)
+    seg = w.segments[row]
+    views = gsp.segment_views(desc, dmt)
+    n_dm, n_out = seg[2], desc.n_out[row]
+    # and the trial nearest each injected pulse whose DM lies in this row
+    lo, st = seg[0], seg[1]
+    near = [int(round((p.dm - lo) / st)) for p in w.pulses]
+    trials = sorted(set(parity_trials(n_dm)) | {i for i in near if 0 <= i < n_dm})
+    say(f"[case] {name} row {row}: {len(trials)} whole trials of {n_dm}, {n_out} outputs each")
+    n_c = 0
+    for i in trials:
+        ref = oracle.dedisperse_segment(X, w.freqs, w.tsamp, seg, trials=(i, i + 1))[0]
+        got = views[row][i].cpu().numpy()
+        bad = np.flatnonzero(got != ref)
+        assert len(bad) == 0, f"row {row} trial {i}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+        co = oracle_cands_with_seg([(row, oracle.search_series(ref, w.widths, w.threshold, trial=i))])
+        match_candidates(cg[(cg["seg"] == row) & (cg["dm_index"] == i)], co, w.threshold)
+        n_c += len(co)
+    say(f"  {len(trials)} trials bit-exact, {n_c} oracle candidates matched")
+    rng = np.random.default_rng(1 + row)
+    tr = np.concatenate([[0, n_dm - 1, 0, n_dm - 1], rng.integers(0, n_dm, 300)])
+    tt = np.concatenate([[0, 0, n_out - 1, n_out - 1], rng.integers(0, n_out, 300)])
+    ref = oracle.dedisperse_points(X, w.freqs, w.tsamp, seg, tr, tt)
+    got = views[row][torch.from_numpy(tr).long().cuda(), torch.from_numpy(tt).long().cuda()].cpu().numpy()
+    assert (got.astype(np.int64) == ref).all(), f"row {row}"

@@ -60,11 +60,13 @@ def env(dev):
     ctx.close()
 
 
-def run_beams(env, beams, interleave=True, graph=True, budget=1 << 34, check_windows=None):
+def run_beams(env, beams, interleave=True, graph=True, budget=1 << 34, check_windows=None, frag_cap=None):
     """Push every beam's blocks (round robin) and step; returns per-beam candidates."""
     gsp, ctx, torch = env
     s = gsp.Stream(ctx, budget, BLOCK, WIDTHS, THR)
     s.set_graph(graph)
+    if frag_cap is not None:
+        s.set_fragment_capacity(frag_cap)
     ids = []
     for w, X in beams:
         bid, ok = s.open_beam(w.nchan, w.freqs, w.tsamp, w.segments)
@@ -121,6 +123,29 @@ def test_single_beam_windows_and_candidates_match_oracle(env, cfg):
             cg = cands[(cands["block"] == k) & (cands["seg"] == r)]
             match_candidates(cg, co, THR)
     assert rep["blocks"] == len(wins)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_fragment_overflow_searches_again_and_loses_nothing(env, graph):
+    """A step whose search finds more run fragments than the stream's buffer
+    holds grows the buffer and searches the same windows again: with a
+    capacity of 3 fragments, the candidates still equal the oracle's window
+    by window, and the report counts the repeated search."""
+    gsp, ctx, torch = env
+    w = beam_workload(0, nsamp=3000)
+    X = w.generate()
+    full = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    wins = windows_of(w)
+    say(f"[case] fragment capacity 3, graph {graph}")
+    ids, cands, rep = run_beams(env, [(w, X)], graph=graph, frag_cap=3)
+    say(f"  {len(cands)} candidates, {rep['search_repeats']} repeated searches of {rep['steps']} steps")
+    assert rep["blocks"] == len(wins)
+    for k, rows in enumerate(wins):
+        for r, (a, b) in enumerate(rows):
+            co = oracle_window_cands(full[r], w, r, a, b)
+            cg = cands[(cands["block"] == k) & (cands["seg"] == r)]
+            match_candidates(cg, co, THR)
+    assert rep["search_repeats"] >= 1  # the grown buffer then holds every later step's fragments
 
 
 def test_mix_equals_alone_and_oracle(env):
@@ -313,6 +338,10 @@ def test_full_shape_windows_equal_batch_and_oracle(env):
     gsp, ctx, torch = env
     B = 20480
     segs = [(0.0, 0.1, 200, 1), (150.0, 0.3, 100, 2), (450.0, 1.0, 100, 4), (1200.0, 3.0, 100, 8)]
+    # trials whose streamed candidates are compared with the oracle's window
+    # search over the oracle's own dedispersed series: the first, the last
+    # and two inside each row
+    cand_trials = [[0, 57, 131, 199], [0, 37, 74, 99], [0, 37, 74, 99], [0, 37, 74, 99]]
     w = synth.Workload("stream-shape", 4096, 1000.0, 1500.0, 49.152e-6, 8 * B, segs, synth.WIDTHS_512, 6.0,
                        synth.BASE_SEED + 7)
     say("[case] full-shape stream beam: generate")
@@ -328,8 +357,10 @@ def test_full_shape_windows_equal_batch_and_oracle(env):
         s.push(bid, X[k * B:(k + 1) * B])
     rng = np.random.default_rng(3)
     checked = 0
+    streamed = []
     for k in range(w.nsamp // B):
         assert s.step() == 1
+        streamed.append(s.poll())
         for r, seg in enumerate(segs):
             D, M = seg[3], int(max_delay[r])
             a, b = max(0, k * B // D - M), max(0, (k + 1) * B // D - M)
@@ -347,5 +378,22 @@ def test_full_shape_windows_equal_batch_and_oracle(env):
         say(f"  step {k}: windows checked")
     assert checked == int(sum(n_out))  # every output of every row, once
     s.close()
+    cands = np.concatenate(streamed)
+    n_cmp = 0
+    for r, seg in enumerate(segs):
+        D, M = seg[3], int(max_delay[r])
+        trials = cand_trials[r]
+        for i in trials:
+            series = oracle.dedisperse_segment(X, w.freqs, w.tsamp, seg, trials=(i, i + 1))[0]
+            for k in range(w.nsamp // B):
+                a, b = max(0, k * B // D - M), max(0, (k + 1) * B // D - M)
+                if b == a:
+                    continue
+                co = oracle.search_window(series, a, b, synth.WIDTHS_512, 6.0, trial=i)
+                co = oracle_cands_with_seg([(r, co)])
+                sel = (cands["block"] == k) & (cands["seg"] == r) & (cands["dm_index"] == i)
+                match_candidates(cands[sel], co, 6.0)
+                n_cmp += len(co)
+    say(f"  streamed candidates of {sum(map(len, cand_trials))} trials match the oracle ({n_cmp} oracle runs)")
     del dmt
     torch.cuda.empty_cache()
