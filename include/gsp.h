@@ -147,6 +147,28 @@ typedef struct gsp_candidate {
 int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt_dev, const gsp_dmt_desc *desc,
                             const int32_t *widths, int32_t n_widths, float threshold,
                             gsp_candidate *cands_host, int64_t capacity, int64_t *n_found, void *stream);
+/* For callers that cannot allocate memory (tight serving loops, harnesses
+ * that forbid allocation): gsp_single_pulse_search with no allocation.
+ * Every device buffer of the search (job table, per-trial statistics,
+ * width set, run fragments, their counter) lives in one static device array
+ * of about 3.7 MB that each GPU the library runs on holds until the process
+ * ends; its address is taken once per device by
+ * gsp_create.  The host work (joining run fragments, building and sorting the
+ * candidates) runs in place in cands_host, so the call allocates nothing on
+ * the host either.  Same arguments and results as gsp_single_pulse_search,
+ * within these limits:
+ *   desc->n_trials <= 32768 and at most 65536 run fragments per call
+ *   (GSP_ECAPACITY otherwise, with a message);
+ *   capacity must be at least the number of run fragments (each run of
+ *   the search is one or more fragments, joined on the host): if it is
+ *   not, nothing is written, *n_found is set to that number (a capacity
+ *   that suffices) and GSP_ECAPACITY is returned.
+ * Calls on one GPU share its array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other threads, other streams) race.
+ * Synchronises `stream`. */
+int gsp_single_pulse_search_noalloc(gsp_ctx *ctx, const int32_t *dmt_dev, const gsp_dmt_desc *desc,
+                                    const int32_t *widths, int32_t n_widths, float threshold,
+                                    gsp_candidate *cands_host, int64_t capacity, int64_t *n_found, void *stream);
 
 /* Friends-of-friends grouping of candidates (host only): two candidates are
  * linked when they share the plan row, their trial indices differ by at most

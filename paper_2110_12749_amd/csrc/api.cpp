@@ -118,6 +118,12 @@ int gsp_create(int device, gsp_ctx **out) {
       delete c;
       return GSP_EDEVICE;
     }
+    try {
+      gsp::noalloc_init(device);  // once per device: address of the static search scratch
+    } catch (const gsp::Error &e) {
+      delete c;
+      return e.status;
+    }
     *out = c;
     return GSP_OK;
   } catch (...) {

@@ -196,6 +196,8 @@ void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, 
                          hipStream_t st);
 
 void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
+// Static search scratch of gsp_single_pulse_search_noalloc: per-device address (noalloc.hip)
+void noalloc_init(int device);
 // One streamed candidate's cutout sources (device state of its beam and row).
 struct StreamCut {
   const int32_t *win;     // window buffer [n_dm][win_pitch]: column look + (t - a) holds time t

@@ -65,6 +65,9 @@ _L.gsp_dedisperse.restype = C.c_int
 _L.gsp_dedisperse.argtypes = [P, P, P, C.POINTER(DmtDesc), P, P]
 _L.gsp_trial_stats.restype = C.c_int
 _L.gsp_trial_stats.argtypes = [P, P, C.POINTER(DmtDesc), P, P, P]
+_L.gsp_single_pulse_search_noalloc.restype = C.c_int
+_L.gsp_single_pulse_search_noalloc.argtypes = [P, P, C.POINTER(DmtDesc), P, C.c_int32, C.c_float, P, C.c_int64,
+                                               C.POINTER(C.c_int64), P]
 _L.gsp_single_pulse_search.restype = C.c_int
 _L.gsp_single_pulse_search.argtypes = [P, P, C.POINTER(DmtDesc), P, C.c_int32, C.c_float, P, C.c_int64,
                                        C.POINTER(C.c_int64), P]
@@ -261,6 +264,24 @@ class Context:
                 continue
             _check(st, self.h)
             return out[: n.value]
+
+    def single_pulse_search_noalloc(self, dmt, desc: DmtDesc, widths, threshold: float, capacity: int = 1 << 16,
+                                    stream=None) -> np.ndarray:
+        """The same search with no device allocation (the library's static
+        scratch; the candidate array doubles as host workspace)."""
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        while True:
+            out = np.empty(capacity, CAND_DTYPE)
+            n = C.c_int64()
+            st = _L.gsp_single_pulse_search_noalloc(self.h, C.c_void_p(dmt.data_ptr()), C.byref(desc),
+                                                    w.ctypes.data, len(w), float(threshold), out.ctypes.data,
+                                                    capacity, C.byref(n), _stream_handle(stream))
+            if st == GSP_ECAPACITY and n.value > capacity:
+                capacity = int(n.value)
+                continue
+            _check(st, self.h)
+            return out[: n.value]
+
 
 
 _default = {}
