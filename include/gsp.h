@@ -86,7 +86,7 @@ typedef struct gsp_dmt_desc {
   int64_t offset[GSP_MAX_SEG];    /* element offset of the row's block */
   int32_t trial0[GSP_MAX_SEG];    /* global index of the row's first trial */
   int32_t n_trials;               /* sum of n_dm */
-  int32_t pad_;
+  int32_t kind;                   /* 0: brute-force plan (gsp_plan_shape); 1: sub-band plan */
   int64_t total;                  /* int32 elements of the whole output */
 } gsp_dmt_desc;
 
@@ -111,6 +111,59 @@ int gsp_delay_table(const gsp_dmt_desc *desc, const double *freqs_mhz, int32_t s
  * The filterbank must stay unchanged until the work on `stream` completes. */
 int gsp_dedisperse(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const gsp_dmt_desc *desc,
                    int32_t *dmt_dev, void *stream);
+
+/* Sub-band (two-stage) dedispersion: the algorithm GSP itself runs (Section
+ * 2.3 names PRESTO's sub-band dedispersion; Tables 2-3 are its survey
+ * plans).  Per plan row s the channels form n_sub[s] bands, band b =
+ * channels [b*nchan/n_sub, (b+1)*nchan/n_sub) with reference frequency f_b =
+ * its highest channel, and the row's trials form groups of group[s]
+ * consecutive trials, group g (n_g trials from trial g*group) with nominal
+ * DM_g = dm_lo + (g*group + (n_g - 1)/2) * dm_step.  With Y the row's
+ * D-downsampled input:
+ *   stage 1: Z[g][b][t] = sum over channels c of band b of Y[c][t + d1(g, c)],
+ *            d1(g, c) = delay of DM_g at f_c against f_b;
+ *   stage 2: dmt[i][t] = sum over bands b of Z[g(i)][b][t + d2(i, b)],
+ *            d2(i, b) = delay of DM_i at f_b against fref;
+ * both delays rounded as in gsp_delay_table with the reference frequency
+ * replaced.  The sums are exact; the composite delays d2 + d1 differ from
+ * the brute-force ones by the in-band smearing of |DM_i - DM_g|.  A row's
+ * valid length is floor(nsamp/D) minus its largest d2(i, b) + max over the
+ * band of d1(g(i), c) (desc->max_delay).  Adds per output: nchan/group + n_sub
+ * instead of nchan.
+ * gsp_subband_plan_shape: as gsp_plan_shape, for a sub-band plan (host
+ * only; n_sub, group: host int32[n_seg]); sets desc->kind = 1.  GSP_EINVAL
+ * unless 1 <= n_sub[s] <= nchan, 1 <= group[s] <= 64 and
+ * 255 * D * ceil(nchan / n_sub[s]) <= 65535 (16-bit sub-band series).
+ * gsp_dedisperse_subband: as gsp_dedisperse, with the same n_sub and group
+ * and a descriptor from gsp_subband_plan_shape; the output feeds
+ * gsp_single_pulse_search and gsp_trial_stats like a brute-force one. */
+int gsp_subband_plan_shape(int64_t nsamp, int32_t nchan, const double *freqs_mhz, double tsamp_s,
+                           const gsp_segment *segs, int32_t n_seg, const int32_t *n_sub, const int32_t *group,
+                           gsp_dmt_desc *desc);
+int gsp_dedisperse_subband(gsp_ctx *ctx, const uint8_t *fb_dev, const double *freqs_mhz, const gsp_dmt_desc *desc,
+                           const int32_t *n_sub, const int32_t *group, int32_t *dmt_dev, void *stream);
+
+/* RFI mitigation of a filterbank, integers throughout (Section 2.1 lists RFI
+ * mitigation among the search steps; Section 3.1 tests PRESTO's clip option
+ * on CPU and GPU; the paper defines neither operation, so this is the
+ * reading taken).
+ *   clip (clip_sigma > 0): spectra in blocks of `block` (the last may be
+ *     shorter).  Per block, the zero-DM series s_j = sum_c x[j][c] has
+ *     population mean mu and sigma from exact integer moments; spectrum j
+ *     is flagged when |s_j - mu| > clip_sigma * sigma (double).  If some
+ *     but not all of the block's spectra are flagged, each flagged one
+ *     becomes the block's channel means over its n_u unflagged spectra,
+ *     m_c = floor((2 S_c + n_u) / (2 n_u)), S_c their channel sums.
+ *   zero-DM filter (zero_dm != 0), after clipping: the rounded mean
+ *     z_j = floor((2 s'_j + nchan) / (2 nchan)) of each (clipped) spectrum is
+ *     subtracted and 128 added back, clamped to 0..255.
+ * fb_dev, out_dev: device uint8 [nsamp][nchan] (time-major); out_dev may be
+ * fb_dev (in place) but must not overlap it otherwise.  n_flagged (host,
+ * optional): spectra replaced by the clip; when given, the call synchronises
+ * `stream`, otherwise it is asynchronous.  GSP_EINVAL for bad sizes,
+ * clip_sigma < 0 or not finite, block outside [1, 2^30] when clipping. */
+int gsp_rfi_clean(gsp_ctx *ctx, const uint8_t *fb_dev, int64_t nsamp, int32_t nchan, double clip_sigma, int64_t block,
+                  int32_t zero_dm, uint8_t *out_dev, int64_t *n_flagged, void *stream);
 
 /* Population mean and sigma of every trial's series over its n_out samples,
  * from exact integer moments about the series' first sample.
@@ -176,6 +229,88 @@ int gsp_single_pulse_search_noalloc(gsp_ctx *ctx, const int32_t *dmt_dev, const 
  * the representative of k's group: the member of highest snr (ties -> lower
  * dm_index, then earlier t_peak).  Returns the number of groups via n_groups. */
 int gsp_group_candidates(const gsp_candidate *cands, int64_t n, int64_t *rep_out, int64_t *n_groups);
+
+/* ---- Sifting: ranking of grouped events, and the candidate store ----
+ *
+ * The paper sifts single-pulse events with RRATtrap (Section 2.2: events of
+ * nearby DMs and times are grouped, the groups ranked and scored by rules;
+ * Section 3.2: groups of rank 3 to 6, 6 the best, and a class of RFI or
+ * noise) without stating the rules.  The reading taken here, per group of
+ * gsp_group_candidates (members of one plan row):
+ *   n_events members, n_trials distinct trials, DM range [dm_min, dm_max];
+ *   the peak is the representative (dm_peak, snr_max, time_s, width_s =
+ *   width * D * tsamp); the group spans start_s = min over members of
+ *   (t_first - width + 1) * D * tsamp to max (t_last + 1) * D * tsamp;
+ *   snr_lo, snr_hi = best member SNR at dm_min and at dm_max.
+ *   rank 2 (RFI):   dm_peak < 1 pc cm^-3;
+ *   rank 1 (noise): otherwise, n_trials < 3;
+ *   else with f = min(1 - snr_lo/snr_max, 1 - snr_hi/snr_max), the fall-off
+ *   of SNR toward both ends of the DM range (in double): rank 3 if f < 0.1,
+ *   4 if f < 0.2, 5 if f < 0.35, otherwise 6. */
+typedef struct gsp_group_record {
+  int64_t rep;             /* index of the representative (peak) candidate */
+  int32_t seg, rank;
+  int32_t n_events, n_trials;
+  double dm_min, dm_max, dm_peak;
+  float snr_max, snr_lo, snr_hi;
+  int32_t reserved;
+  double time_s, width_s, start_s, duration_s;
+} gsp_group_record;
+/* Host only.  cands and rep (host, n entries: rep from gsp_group_candidates)
+ * and the plan's descriptor in; one record per group out (host array of cap),
+ * in order of the representative's index; *n_groups = number of groups
+ * (GSP_ECAPACITY when it exceeds cap).  GSP_EINVAL if rep is not a grouping
+ * (rep[rep[k]] == rep[k] for every k). */
+int gsp_rank_groups(const gsp_candidate *cands, int64_t n, const int64_t *rep, const gsp_dmt_desc *desc,
+                    gsp_group_record *out, int64_t cap, int64_t *n_groups);
+
+/* Candidate store with the six tables of the paper's database (Section 2.2):
+ *   T_FITS_INFO               one row per processed input (name, beam, nchan,
+ *                             nsamp, tsamp, band edges);
+ *   T_SINGLEPULSE_GROUPS      one row per input: candidates, groups, groups per rank;
+ *   T_SINGLEPULSE_CANDIDATES  one row per ranked group (gsp_group_record);
+ *   T_PULSAR                  known sources (name, DM) entered by the caller;
+ *   T_FILE_PULSAR             known sources matched by DM to an input's groups;
+ *   T_SINGLEPULSE_PIC         a picture path per candidate (e.g. its cutout).
+ * Kept in host memory; gsp_store_save / gsp_store_load write and read one CSV
+ * file per table (named as above) in a directory.  Ids start at 1.  Names and
+ * paths must not hold commas, quotes or line breaks (GSP_EINVAL).  Not
+ * thread-safe: one caller at a time. */
+enum {
+  GSP_T_FITS_INFO = 0,
+  GSP_T_SINGLEPULSE_GROUPS = 1,
+  GSP_T_SINGLEPULSE_CANDIDATES = 2,
+  GSP_T_PULSAR = 3,
+  GSP_T_FILE_PULSAR = 4,
+  GSP_T_SINGLEPULSE_PIC = 5
+};
+typedef struct gsp_store gsp_store;
+typedef struct gsp_store_candidate {
+  int64_t id, file_id;
+  gsp_group_record g;
+} gsp_store_candidate;
+int gsp_store_create(gsp_store **out);
+void gsp_store_destroy(gsp_store *s);
+const char *gsp_store_last_error(const gsp_store *s);
+int gsp_store_add_file(gsp_store *s, const char *name, int32_t beam, int32_t nchan, int64_t nsamp, double tsamp_s,
+                       double f_lo_mhz, double f_hi_mhz, int64_t *file_id);
+/* The ranked groups of one input (each input once); *first_id = id of the first. */
+int gsp_store_add_groups(gsp_store *s, int64_t file_id, int64_t n_candidates, const gsp_group_record *groups,
+                         int64_t n, int64_t *first_id);
+int gsp_store_add_pulsar(gsp_store *s, const char *name, double dm, int64_t *pulsar_id);
+/* Replaces the input's T_FILE_PULSAR rows: every known source with at least
+ * one stored group of rank >= min_rank whose dm_peak lies within dm_tol of its
+ * DM (with the number of such groups and their best SNR). */
+int gsp_store_match_pulsars(gsp_store *s, int64_t file_id, double dm_tol, int32_t min_rank, int64_t *n_matches);
+int gsp_store_add_picture(gsp_store *s, int64_t cand_id, const char *path);
+/* Stored candidates with rank >= min_rank and dm_lo <= dm_peak <= dm_hi, in
+ * id order (GSP_ECAPACITY with *n = count when more than cap). */
+int gsp_store_query(gsp_store *s, int32_t min_rank, double dm_lo, double dm_hi, gsp_store_candidate *out,
+                    int64_t cap, int64_t *n);
+int gsp_store_count(const gsp_store *s, int32_t table, int64_t *n);
+int gsp_store_save(gsp_store *s, const char *dir);
+/* Replaces the store's contents with the tables in dir. */
+int gsp_store_load(gsp_store *s, const char *dir);
 
 /* ---- Streaming: continuous batching of beams arriving in blocks ----
  *

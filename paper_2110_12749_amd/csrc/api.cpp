@@ -201,6 +201,7 @@ int gsp_dedisperse(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const g
   return guarded(ctx, [&] {
     validate_desc(desc);
     if (!fb || !freqs || !dmt) fail(GSP_EINVAL, "null pointer argument");
+    if (desc->kind != 0) fail(GSP_EINVAL, "sub-band descriptor: use gsp_dedisperse_subband");
     if (fref_of(freqs, desc->nchan) != desc->fref_mhz)
       fail(GSP_EINVAL, "frequencies differ from those the plan was shaped with");
     hipStream_t st = static_cast<hipStream_t>(stream);

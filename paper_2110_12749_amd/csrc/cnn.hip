@@ -1264,6 +1264,7 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
   return guarded(ctx, [&] {
     validate_desc(desc);
     if (!fb || !freqs || !dmt || (n > 0 && (!cands || !out)) || n < 0) fail(GSP_EINVAL, "bad arguments");
+    if (desc->kind != 0) fail(GSP_EINVAL, "cutouts take a brute-force plan's output");
     if (n == 0) return;
     hipStream_t st = static_cast<hipStream_t>(stream);
     launch_stats(ctx, dmt, desc, st);  // per-trial means for padding before the start

@@ -214,20 +214,30 @@ int64_t staged_pitch(const RowTables &rt) {
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
                       const DedispShape &shape, RowTables &rt, int units_per_thread) {
   const gsp_segment &g = desc->seg[s];
-  rt.n_dm = g.n_dm;
-  rt.D = g.downsamp;
-  rt.nchan = desc->nchan;
-  rt.N = desc->nsamp / g.downsamp;
-  rt.n_out = desc->n_out[s];
-  rt.max_delay = desc->max_delay[s];
+  if (rt.delays_host.empty()) {
+    rt.delays_host.resize((size_t)g.n_dm * desc->nchan);
+    compute_delays(desc, freqs, s, rt.delays_host.data());
+  }
+  build_tables_from_delays(ctx, g.n_dm, desc->nchan, g.downsamp, desc->nsamp / g.downsamp, desc->n_out[s],
+                           desc->max_delay[s], shape, rt, units_per_thread);
+}
+
+void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_t D, int64_t N, int64_t n_out,
+                              int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread) {
+  struct {
+    int32_t n_dm, downsamp;
+  } g{n_dm, D};
+  rt.n_dm = n_dm;
+  rt.D = D;
+  rt.nchan = nchan_;
+  rt.N = N;
+  rt.n_out = n_out;
+  rt.max_delay = max_delay;
   rt.shape = shape;
   rt.addr.device = ctx->device;
   rt.dmin.device = ctx->device;
-  const int nchan = desc->nchan;
-  if (rt.delays_host.empty()) {
-    rt.delays_host.resize((size_t)g.n_dm * nchan);
-    compute_delays(desc, freqs, s, rt.delays_host.data());
-  }
+  const int nchan = nchan_;
+  if (rt.delays_host.size() != (size_t)n_dm * nchan) fail(GSP_EINVAL, "delay table size");
   const int MT = shape.trials_per_block();
   const int n_tiles = (g.n_dm + MT - 1) / MT;
   const int n_dm_pad = n_tiles * MT;
@@ -321,8 +331,9 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
   check_hip(hipMemcpy(rt.dmin.ptr, base.data(), base.size() * 4, hipMemcpyHostToDevice), "copy staging bases");
 }
 
-void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st) {
-  const int64_t pitch = staged_pitch(rt);
+void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st,
+               int64_t pitch_override) {
+  const int64_t pitch = pitch_override > 0 ? pitch_override : staged_pitch(rt);
   const size_t elem = rt.D == 1 ? 1 : 2;
   ctx->staged.device = ctx->device;
   ctx->staged.reserve((size_t)pitch * rt.nchan * elem + 256);

@@ -11,7 +11,7 @@ struct DedispArgs {
   int64_t pitch;            // elements per channel row of Y
   const uint32_t *addr;     // [nchan][n_dm_pad] LDS dword offsets
   const int32_t *base;      // [n_tiles_dm][nchan] staging start (delay of tile's first trial, /4*4)
-  int32_t *out;             // out[i * out_pitch + (t - t_lo)] for t in [t_lo, t_hi)
+  void *out;                // OutT out[i * out_pitch + (t - t_lo)] for t in [t_lo, t_hi)
   int64_t out_pitch;
   int64_t t_origin;         // absolute output index of tile 0's first sample (multiple of 4)
   int64_t t_lo, t_hi;       // outputs stored
@@ -56,7 +56,9 @@ struct Unit {
 
 // One tile: trials [dm_tile*MT, +MT) x outputs t0 + [0, 128*K) with
 // t0 = t_origin + t_tile * 128*K.  Every thread of the workgroup calls it.
-template <int K, int TPW, typename SrcT>
+// OutT: int32_t, or uint16_t where every sum is known to fit 16 bits (the
+// sub-band series of sub-band dedispersion).
+template <int K, int TPW, typename SrcT, typename OutT = int32_t>
 __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, int t_tile, uint32_t *lds) {
   static_assert(TPW % 4 == 0, "offsets are read four trials at a time");
   const int tid = threadIdx.x;
@@ -279,12 +281,12 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
   for (int j = 0; j < TPW; ++j) {
     const int i = i_wave + j;
     if (i >= a.n_dm) break;
-    int32_t *orow_out = a.out + (int64_t)i * a.out_pitch - a.t_lo;
+    OutT *orow_out = static_cast<OutT *>(a.out) + (int64_t)i * a.out_pitch - a.t_lo;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
-      if (t >= a.t_lo && t < a.t_hi) orow_out[t] = tot[j][k][0];
-      if (t + 1 >= a.t_lo && t + 1 < a.t_hi) orow_out[t + 1] = tot[j][k][1];
+      if (t >= a.t_lo && t < a.t_hi) orow_out[t] = (OutT)tot[j][k][0];
+      if (t + 1 >= a.t_lo && t + 1 < a.t_hi) orow_out[t + 1] = (OutT)tot[j][k][1];
     }
   }
 }

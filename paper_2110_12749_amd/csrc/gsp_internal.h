@@ -121,6 +121,7 @@ struct SearchTiling {
 struct gsp_ctx;
 
 namespace gsp {
+struct SubbandPlan;  // cached tables of a sub-band plan (subband.hip)
 // Run f at the ABI boundary: select the context's device, turn every error
 // into a status code and keep its message on the context.
 template <class F>
@@ -138,6 +139,9 @@ struct gsp_ctx {
   gsp::DevBuf widths;      // device copy of the width set
   gsp::DevBuf jobs;        // device copy of the series-job table
   gsp::DevBuf ftsums;      // frequency-time band sums of batch cutouts
+  gsp::DevBuf rfi;         // RFI mitigation: spectrum sums, flags, block means
+  gsp::DevBuf zbuf;        // sub-band series of sub-band dedispersion
+  std::map<std::string, std::shared_ptr<gsp::SubbandPlan>> subband;
   std::unique_ptr<gsp::SeriesTable> jobs_host = std::make_unique<gsp::SeriesTable>();
   std::vector<uint8_t> host_scratch;
   // tuned shapes keyed by row signature
@@ -180,7 +184,14 @@ DedispShape shape_for_row(gsp_ctx *ctx, const gsp_dmt_desc *desc, int32_t s);
 // unit_max for its source type); 0 = the batch kernel's for the row's D
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
                       const DedispShape &shape, RowTables &rt, int units_per_thread = 0);
-void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st);
+// The same tables from an explicit delay table rt.delays_host [n_dm][nchan]
+// (delays of D*tsamp samples, max_delay their largest; n_out outputs).
+void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan, int32_t D, int64_t N, int64_t n_out,
+                              int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread = 0);
+// pitch_override > 0: stage with that pitch (elements per channel row, a
+// multiple of 256 covering every read of the kernels that use the copy)
+void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st,
+               int64_t pitch_override = 0);
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 int64_t staged_pitch(const RowTables &rt);
 
@@ -196,6 +207,9 @@ void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, 
                          hipStream_t st);
 
 void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
+// Sub-band dedispersion (subband.hip)
+void subband_plan_shape(int64_t nsamp, int32_t nchan, const double *freqs, double tsamp, const gsp_segment *segs,
+                        int32_t n_seg, const int32_t *n_sub, const int32_t *group, gsp_dmt_desc *desc);
 // Static search scratch of gsp_single_pulse_search_noalloc: per-device address (noalloc.hip)
 void noalloc_init(int device);
 // One streamed candidate's cutout sources (device state of its beam and row).

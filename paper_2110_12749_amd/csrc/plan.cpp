@@ -48,6 +48,7 @@ void validate_desc(const gsp_dmt_desc *d) {
   if (!d) fail(GSP_EINVAL, "null plan descriptor");
   if (d->nsamp < 1 || d->nchan < 1 || !finite_pos(d->tsamp) || d->n_seg < 1 || d->n_seg > GSP_MAX_SEG)
     fail(GSP_EINVAL, "plan descriptor is not shaped (call gsp_plan_shape)");
+  if (d->kind != 0 && d->kind != 1) fail(GSP_EINVAL, "plan descriptor kind must be 0 or 1");
   int64_t off = 0;
   int32_t t0 = 0;
   for (int32_t s = 0; s < d->n_seg; ++s) {

@@ -34,7 +34,7 @@ class DmtDesc(C.Structure):
     _fields_ = [("nsamp", C.c_int64), ("nchan", C.c_int32), ("n_seg", C.c_int32), ("tsamp", C.c_double),
                 ("fref_mhz", C.c_double), ("seg", Segment * MAX_SEG), ("max_delay", C.c_int64 * MAX_SEG),
                 ("n_out", C.c_int64 * MAX_SEG), ("offset", C.c_int64 * MAX_SEG), ("trial0", C.c_int32 * MAX_SEG),
-                ("n_trials", C.c_int32), ("pad_", C.c_int32), ("total", C.c_int64)]
+                ("n_trials", C.c_int32), ("kind", C.c_int32), ("total", C.c_int64)]
 
 
 class Candidate(C.Structure):
@@ -63,6 +63,29 @@ _L.gsp_delay_table.restype = C.c_int
 _L.gsp_delay_table.argtypes = [C.POINTER(DmtDesc), P, C.c_int32, P]
 _L.gsp_dedisperse.restype = C.c_int
 _L.gsp_dedisperse.argtypes = [P, P, P, C.POINTER(DmtDesc), P, P]
+_L.gsp_subband_plan_shape.restype = C.c_int
+_L.gsp_subband_plan_shape.argtypes = [C.c_int64, C.c_int32, P, C.c_double, P, C.c_int32, P, P, C.POINTER(DmtDesc)]
+_L.gsp_dedisperse_subband.restype = C.c_int
+_L.gsp_dedisperse_subband.argtypes = [P, P, P, C.POINTER(DmtDesc), P, P, P, P]
+_L.gsp_rank_groups.restype = C.c_int
+_L.gsp_rank_groups.argtypes = [P, C.c_int64, P, C.POINTER(DmtDesc), P, C.c_int64, C.POINTER(C.c_int64)]
+for _n, _a in (("gsp_store_create", [P]), ("gsp_store_add_file", [P, C.c_char_p, C.c_int32, C.c_int32, C.c_int64,
+                                                                   C.c_double, C.c_double, C.c_double, P]),
+               ("gsp_store_add_groups", [P, C.c_int64, C.c_int64, P, C.c_int64, P]),
+               ("gsp_store_add_pulsar", [P, C.c_char_p, C.c_double, P]),
+               ("gsp_store_match_pulsars", [P, C.c_int64, C.c_double, C.c_int32, P]),
+               ("gsp_store_add_picture", [P, C.c_int64, C.c_char_p]),
+               ("gsp_store_query", [P, C.c_int32, C.c_double, C.c_double, P, C.c_int64, P]),
+               ("gsp_store_count", [P, C.c_int32, P]), ("gsp_store_save", [P, C.c_char_p]),
+               ("gsp_store_load", [P, C.c_char_p])):
+    getattr(_L, _n).restype = C.c_int
+    getattr(_L, _n).argtypes = _a
+_L.gsp_store_destroy.restype = None
+_L.gsp_store_destroy.argtypes = [P]
+_L.gsp_store_last_error.restype = C.c_char_p
+_L.gsp_store_last_error.argtypes = [P]
+_L.gsp_rfi_clean.restype = C.c_int
+_L.gsp_rfi_clean.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double, C.c_int64, C.c_int32, P, C.POINTER(C.c_int64), P]
 _L.gsp_trial_stats.restype = C.c_int
 _L.gsp_trial_stats.argtypes = [P, P, C.POINTER(DmtDesc), P, P, P]
 _L.gsp_single_pulse_search_noalloc.restype = C.c_int
@@ -144,6 +167,25 @@ def plan_shape(nsamp: int, freqs, tsamp: float, segments) -> DmtDesc:
     return d
 
 
+def _row_ints(v, n_seg, what):
+    a = np.full(n_seg, int(v), np.int32) if np.isscalar(v) else np.ascontiguousarray(v, dtype=np.int32)
+    assert a.shape == (n_seg,), what
+    return a
+
+
+def subband_plan_shape(nsamp: int, freqs, tsamp: float, segments, n_sub, group) -> DmtDesc:
+    """Descriptor of a sub-band plan (gsp_subband_plan_shape); n_sub and
+    group: one value for every row, or one per row."""
+    f = _f64(freqs)
+    d = DmtDesc()
+    segs = _segs(segments)
+    ns = _row_ints(n_sub, len(segments), "n_sub")
+    gr = _row_ints(group, len(segments), "group")
+    _check(_L.gsp_subband_plan_shape(int(nsamp), len(f), f.ctypes.data, float(tsamp), C.addressof(segs),
+                                     len(segments), ns.ctypes.data, gr.ctypes.data, C.byref(d)))
+    return d
+
+
 def delay_table(desc: DmtDesc, freqs, seg: int) -> np.ndarray:
     f = _f64(freqs)
     out = np.empty((desc.seg[seg].n_dm, desc.nchan), np.int32)
@@ -165,6 +207,97 @@ def group_candidates(cands: np.ndarray):
     ng = C.c_int64()
     _check(_L.gsp_group_candidates(c.ctypes.data, len(c), rep.ctypes.data, C.byref(ng)))
     return rep, int(ng.value)
+
+
+GROUP_DTYPE = np.dtype([("rep", np.int64), ("seg", np.int32), ("rank", np.int32), ("n_events", np.int32),
+                        ("n_trials", np.int32), ("dm_min", np.float64), ("dm_max", np.float64),
+                        ("dm_peak", np.float64), ("snr_max", np.float32), ("snr_lo", np.float32),
+                        ("snr_hi", np.float32), ("reserved", np.int32), ("time_s", np.float64),
+                        ("width_s", np.float64), ("start_s", np.float64), ("duration_s", np.float64)])
+STORE_CAND_DTYPE = np.dtype([("id", np.int64), ("file_id", np.int64), ("g", GROUP_DTYPE)])
+T_FITS_INFO, T_SINGLEPULSE_GROUPS, T_SINGLEPULSE_CANDIDATES, T_PULSAR, T_FILE_PULSAR, T_SINGLEPULSE_PIC = range(6)
+
+
+def rank_groups(cands: np.ndarray, rep, desc: DmtDesc) -> np.ndarray:
+    """Ranked groups (GROUP_DTYPE), one per group of gsp_group_candidates."""
+    c = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    r = np.ascontiguousarray(rep, dtype=np.int64)
+    cap = max(1, len(np.unique(r))) if len(r) else 1
+    out = np.zeros(cap, GROUP_DTYPE)
+    n = C.c_int64()
+    _check(_L.gsp_rank_groups(c.ctypes.data, len(c), r.ctypes.data, C.byref(desc), out.ctypes.data, cap,
+                              C.byref(n)))
+    return out[: n.value]
+
+
+class Store:
+    """Candidate store with the paper's six tables (gsp_store_*)."""
+
+    def __init__(self):
+        self.h = P()
+        _check(_L.gsp_store_create(C.byref(self.h)))
+
+    def _check(self, st):
+        if st != GSP_OK:
+            raise GspError(st, _L.gsp_store_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            _L.gsp_store_destroy(self.h)
+            self.h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_file(self, name, beam, nchan, nsamp, tsamp, f_lo, f_hi) -> int:
+        i = C.c_int64()
+        self._check(_L.gsp_store_add_file(self.h, name.encode(), int(beam), int(nchan), int(nsamp), float(tsamp),
+                                          float(f_lo), float(f_hi), C.byref(i)))
+        return int(i.value)
+
+    def add_groups(self, file_id, n_candidates, groups) -> int:
+        g = np.ascontiguousarray(groups, dtype=GROUP_DTYPE)
+        i = C.c_int64()
+        self._check(_L.gsp_store_add_groups(self.h, int(file_id), int(n_candidates), g.ctypes.data, len(g),
+                                            C.byref(i)))
+        return int(i.value)
+
+    def add_pulsar(self, name, dm) -> int:
+        i = C.c_int64()
+        self._check(_L.gsp_store_add_pulsar(self.h, name.encode(), float(dm), C.byref(i)))
+        return int(i.value)
+
+    def match_pulsars(self, file_id, dm_tol, min_rank=3) -> int:
+        n = C.c_int64()
+        self._check(_L.gsp_store_match_pulsars(self.h, int(file_id), float(dm_tol), int(min_rank), C.byref(n)))
+        return int(n.value)
+
+    def add_picture(self, cand_id, path):
+        self._check(_L.gsp_store_add_picture(self.h, int(cand_id), path.encode()))
+
+    def query(self, min_rank=1, dm_lo=-np.inf, dm_hi=np.inf) -> np.ndarray:
+        n = C.c_int64()
+        st = _L.gsp_store_query(self.h, int(min_rank), float(dm_lo), float(dm_hi), None, 0, C.byref(n))
+        if st not in (GSP_OK, GSP_ECAPACITY):
+            self._check(st)
+        out = np.zeros(max(1, n.value), STORE_CAND_DTYPE)
+        self._check(_L.gsp_store_query(self.h, int(min_rank), float(dm_lo), float(dm_hi), out.ctypes.data,
+                                       len(out), C.byref(n)))
+        return out[: n.value]
+
+    def count(self, table) -> int:
+        n = C.c_int64()
+        self._check(_L.gsp_store_count(self.h, int(table), C.byref(n)))
+        return int(n.value)
+
+    def save(self, path):
+        self._check(_L.gsp_store_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(_L.gsp_store_load(self.h, str(path).encode()))
 
 
 class Context:
@@ -239,12 +372,44 @@ class Context:
                                  C.c_void_p(out.data_ptr()), _stream_handle(stream)), self.h)
         return out
 
+    def dedisperse_subband(self, fb, freqs, desc: DmtDesc, n_sub, group, out=None, stream=None):
+        """Sub-band dedispersion (desc from subband_plan_shape with the same
+        n_sub and group).  Returns int32 [total]."""
+        import torch
+        assert fb.dtype == torch.uint8 and fb.is_cuda and fb.is_contiguous()
+        assert tuple(fb.shape) == (desc.nsamp, desc.nchan)
+        if out is None:
+            out = torch.empty(desc.total, dtype=torch.int32, device=fb.device)
+        assert out.dtype == torch.int32 and out.is_contiguous() and out.numel() >= desc.total
+        f = _f64(freqs)
+        ns = _row_ints(n_sub, desc.n_seg, "n_sub")
+        gr = _row_ints(group, desc.n_seg, "group")
+        _check(_L.gsp_dedisperse_subband(self.h, C.c_void_p(fb.data_ptr()), f.ctypes.data, C.byref(desc),
+                                         ns.ctypes.data, gr.ctypes.data, C.c_void_p(out.data_ptr()),
+                                         _stream_handle(stream)), self.h)
+        return out
+
     def trial_stats(self, dmt, desc: DmtDesc, stream=None):
         mu = np.empty(desc.n_trials, np.float64)
         sg = np.empty(desc.n_trials, np.float64)
         _check(_L.gsp_trial_stats(self.h, C.c_void_p(dmt.data_ptr()), C.byref(desc), mu.ctypes.data, sg.ctypes.data,
                                   _stream_handle(stream)), self.h)
         return mu, sg
+
+    def rfi_clean(self, fb, clip_sigma: float = 0.0, block: int = 2048, zero_dm: bool = False, out=None,
+                  count: bool = True, stream=None):
+        """RFI mitigation of a device uint8 [nsamp][nchan] filterbank (in
+        place when out is fb).  Returns (out, spectra replaced by the clip,
+        or None with count=False: then the call stays asynchronous)."""
+        import torch
+        assert fb.is_cuda and fb.dtype == torch.uint8 and fb.dim() == 2 and fb.is_contiguous()
+        if out is None:
+            out = torch.empty_like(fb)
+        n = C.c_int64()
+        _check(_L.gsp_rfi_clean(self.h, C.c_void_p(fb.data_ptr()), fb.shape[0], fb.shape[1], float(clip_sigma),
+                                int(block), int(bool(zero_dm)), C.c_void_p(out.data_ptr()),
+                                C.byref(n) if count else None, _stream_handle(stream)), self.h)
+        return out, (int(n.value) if count else None)
 
     def single_pulse_search(self, dmt, desc: DmtDesc, widths, threshold: float, capacity: int = 1 << 16,
                             stream=None) -> np.ndarray:
@@ -281,7 +446,6 @@ class Context:
                 continue
             _check(st, self.h)
             return out[: n.value]
-
 
 
 _default = {}

@@ -126,3 +126,32 @@ def test_grouping_matches_oracle(gsp):
             og = oracle.group(oc)
             assert (idx[og] == rep[idx]).all()
         assert ng == len(np.unique(rep))
+
+
+def test_subband_plan_shape_matches_oracle(gsp):
+    """Sub-band plans: per-row valid lengths and largest composite delays
+    equal the oracle's; the descriptor is marked as a sub-band plan; the
+    16-bit limit on the sub-band series and bad n_sub / group are rejected."""
+    w = synth.realistic()
+    n_sub, group = [64, 64, 64, 128], [8, 16, 16, 16]
+    d = gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, group)
+    assert d.kind == 1
+    off = 0
+    for s, seg in enumerate(w.segments):
+        dd, n_out = oracle.subband_delays(w.freqs, w.nsamp, w.tsamp, seg, n_sub[s], group[s])
+        assert d.n_out[s] == n_out
+        assert d.max_delay[s] == w.nsamp // seg[3] - n_out
+        assert d.offset[s] == off
+        off += seg[2] * n_out
+    assert d.total == off
+    assert gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments).kind == 0
+    for bad in ([64, 64, 64, 64], [0, 64, 64, 128], [64, 64, 64, 4097]):  # D = 8 with 64 channels per band; range
+        with pytest.raises(gsp.GspError) as e:
+            gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, bad, 16)
+        assert e.value.status == gsp.GSP_EINVAL
+    for bad in (0, 65):
+        with pytest.raises(gsp.GspError):
+            gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, bad)
+    with pytest.raises(gsp.GspError) as e:
+        gsp.subband_plan_shape(20000, w.freqs, w.tsamp, w.segments, n_sub, 16)
+    assert e.value.status == gsp.GSP_ETOOSHORT

@@ -1,0 +1,124 @@
+"""Sub-band (two-stage) dedispersion on the GPU against its oracle
+(oracle.dedisperse_subband): bit-exact integer sums on small plans (unequal
+bands, ragged last groups, D = 1..8, the special cases that reduce to brute
+force) and on sampled whole trials of the realistic workload at full size;
+then brute force as the accuracy judge: the search of the sub-band output
+keeps the injected pulses' SNR."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_12749_amd import synth
+from tests._util import match_candidates, oracle_cands_with_seg, say
+
+pytestmark = pytest.mark.gpu
+
+# per-row sub-band choices of the realistic plan (D = 1, 2, 4, 8): 16-bit
+# sub-band series need 255 * D * channels per band <= 65535
+REAL_NSUB = [64, 64, 64, 128]
+REAL_GROUP = 16
+
+
+@pytest.fixture(scope="module")
+def env(dev):
+    import torch
+    from paper_2110_12749_amd import gsp
+    ctx = gsp.Context(0)
+    yield gsp, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _run(env, w, X, n_sub, group):
+    gsp, ctx, torch = env
+    desc = gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, group)
+    fb = torch.from_numpy(X).cuda()
+    dmt = ctx.dedisperse_subband(fb, w.freqs, desc, n_sub, group)
+    torch.cuda.synchronize()
+    return desc, dmt
+
+
+@pytest.mark.parametrize("nchan,nsamp,segs,n_sub,group", [
+    (64, 6000, [(0.0, 1.0, 40, 1)], 8, 4),                          # equal bands, 10 groups
+    (100, 7001, [(0.0, 0.7, 45, 1)], 7, 6),                         # unequal bands, ragged last group
+    (96, 9001, [(0.0, 2.0, 33, 2), (66.0, 3.0, 17, 4)], [12, 24], [5, 3]),  # D = 2, 4
+    (128, 12000, [(0.0, 4.0, 20, 8)], 32, 16),                      # D = 8: 4 channels per band
+    (40, 4000, [(0.0, 1.5, 24, 1)], 40, 7),                         # one channel per band: brute force
+    (48, 5000, [(5.0, 1.0, 19, 2)], 1, 1),                          # one band, one-trial groups: brute force
+    (4096, 6000, [(0.0, 0.5, 70, 1), (35.0, 1.0, 40, 4)], [64, 64], [16, 16]),  # the realistic band's width
+])
+def test_small_plans_match_oracle(env, nchan, nsamp, segs, n_sub, group):
+    gsp, ctx, torch = env
+    w = synth.small(nchan=nchan, nsamp=nsamp, segments=segs, n_pulses=2, seed_offset=600 + nchan % 17)
+    X = w.generate()
+    say(f"[case] sub-band {nchan} ch, {nsamp} samples, rows {segs}, n_sub {n_sub}, group {group}")
+    desc, dmt = _run(env, w, X, n_sub, group)
+    views = gsp.segment_views(desc, dmt)
+    ns = [n_sub] * len(segs) if np.isscalar(n_sub) else n_sub
+    gr = [group] * len(segs) if np.isscalar(group) else group
+    for s, seg in enumerate(segs):
+        ref = oracle.dedisperse_subband(X, w.freqs, w.tsamp, seg, ns[s], gr[s])
+        got = views[s].cpu().numpy()
+        assert got.shape == ref.shape, (got.shape, ref.shape)
+        bad = np.argwhere(got != ref)
+        assert len(bad) == 0, f"row {s}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+        if ns[s] == nchan or (ns[s] == 1 and gr[s] == 1):
+            assert np.array_equal(got, oracle.dedisperse_segment(X, w.freqs, w.tsamp, seg))
+
+
+@pytest.fixture(scope="module")
+def realistic(env):
+    gsp, ctx, torch = env
+    w = synth.realistic()
+    say("[case] sub-band realistic full size: generate")
+    X = w.generate()
+    desc, dmt = _run(env, w, X, REAL_NSUB, REAL_GROUP)
+    cands = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold)
+    yield w, X, desc, dmt, cands
+    del dmt
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("row", [0, 1, 2, 3])
+def test_realistic_rows_match_oracle(env, realistic, row):
+    """Whole series of the first, the last and every 97th trial of the row
+    bit-exact against the oracle's two stages, and the search's candidates
+    of those trials against the oracle's search of its series."""
+    gsp, ctx, torch = env
+    w, X, desc, dmt, cands = realistic
+    seg = w.segments[row]
+    n_dm = seg[2]
+    trials = sorted(set([0, n_dm - 1] + list(range(0, n_dm, 97))))
+    views = gsp.segment_views(desc, dmt)
+    say(f"[case] sub-band realistic row {row}: {len(trials)} trials")
+    for i in trials:
+        ref = oracle.dedisperse_subband(X, w.freqs, w.tsamp, seg, REAL_NSUB[row], REAL_GROUP, trials=(i, i + 1))[0]
+        got = views[row][i].cpu().numpy()
+        bad = np.flatnonzero(got != ref)
+        assert len(bad) == 0, f"trial {i}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+        co = oracle_cands_with_seg([(row, oracle.search_series(ref, w.widths, w.threshold, trial=i))])
+        match_candidates(cands[(cands["seg"] == row) & (cands["dm_index"] == i)], co, w.threshold)
+
+
+def test_realistic_pulses_keep_their_snr(env, realistic):
+    """Brute force judges the approximation: for every injected pulse the
+    best candidate of the sub-band output near the pulse's DM and time has
+    at least 0.9 of the brute-force search's best SNR there."""
+    gsp, ctx, torch = env
+    w, X, desc, dmt, sub = realistic
+    fb = torch.from_numpy(X).cuda()
+    bdesc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    bdmt = ctx.dedisperse(fb, w.freqs, bdesc)
+    brute = ctx.single_pulse_search(bdmt, bdesc, w.widths, w.threshold)
+    del bdmt
+    ratios = []
+    for p in w.pulses:
+        def best(c):
+            near = c[(np.abs(c["dm"] - p.dm) <= max(2.0, 0.05 * p.dm)) & (np.abs(c["time_s"] - p.t0_s) < 0.1 + 3 * p.fwhm_s)]
+            return float(near["snr"].max()) if len(near) else 0.0
+        b, s = best(brute), best(sub)
+        if b >= 8.0:
+            ratios.append(s / b)
+            say(f"  pulse DM {p.dm:7.1f} FWHM {p.fwhm_s * 1e3:5.2f} ms: brute {b:6.2f} sub-band {s:6.2f}")
+    assert len(ratios) >= 10
+    assert min(ratios) >= 0.9, ratios
