@@ -107,11 +107,39 @@ def cpu_baseline(w, X, desc, every: int):
         t_full += dt * seg[2] / len(idx)
         log(f"  cpu row {s}: {len(idx)} trials in {dt:.2f} s")
     total = sum(desc.seg[s].n_dm * desc.n_out[s] for s in range(desc.n_seg))
-    return {"value": total / t_full, "unit": "DM-trial×samples/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # one core: the first trial of each row, extrapolated the same way
+    oracle.set_threads(1)
+    t1_full, t1_all = 0.0, 0.0
+    for s, seg in enumerate(w.segments):
+        t0 = time.perf_counter()
+        row = oracle.dedisperse_segment(X, w.freqs, w.tsamp, seg, trials=(0, 1))
+        oracle.search_series(row[0], w.widths, w.threshold, trial=0)
+        dt = time.perf_counter() - t0
+        t1_all += dt
+        t1_full += dt * seg[2]
+        log(f"  cpu row {s} on one core: 1 trial in {dt:.2f} s")
+    oracle.set_threads(cores)
+    return {"value": total / t_full, "unit": "DM-trial×samples/s", "cores": cores,
             "kind": "oracle",
             "sample": f"every {every}th trial of each DDplan row ({sampled} of {w.n_trials} trials, full length), "
                       f"dedispersion + boxcar search, {t_all:.1f} s measured, extrapolated per row to the full plan",
-            "rtf": (w.nsamp * w.tsamp) / t_full}
+            "rtf": (w.nsamp * w.tsamp) / t_full,
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "one_core": {"value": total / t1_full, "rtf": (w.nsamp * w.tsamp) / t1_full,
+                         "sample": f"the first trial of each row on one thread ({t1_all:.1f} s measured), "
+                                   f"extrapolated per row"}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = None, triage: str | None = None,
@@ -135,9 +163,10 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
     ctx = gsp.Context(0)
     s = gsp.Stream(ctx, 200 << 30, B, synth.WIDTHS_512, 6.0)
     net = None
-    if triage:  # trained network weights (gsp_cnn_save) scoring each step's candidates
-        net = gsp.Cnn(ctx)
-        net.load(triage)
+    if triage:  # network weights (a gsp_cnn_save file, or "random": timing only) scoring each step's candidates
+        net = gsp.Cnn(ctx, seed=1)
+        if triage != "random":
+            net.load(triage)
         s.set_triage(net, triage_thr)
     ids = []
     for w in beams:
@@ -194,6 +223,53 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
             "triage": None if net is None else {
                 "threshold": triage_thr, "scored": int(rep["triage_scored"]), "rejected": int(rep["triage_rejected"]),
                 "ms_per_block": rep["triage_s"] / max(1, rep["blocks"]) * 1e3}}
+
+
+SUBBAND_NSUB = {1: 64, 2: 64, 4: 64, 8: 128}  # bands per row by downsampling (16-bit sub-band series)
+SUBBAND_GROUP = 16
+
+
+def bench_subband(ctx, w, fb, stream, steps):
+    """The step with sub-band (two-stage) dedispersion instead of brute
+    force: staging, both stages, statistics, search, grouping."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    n_sub = [SUBBAND_NSUB.get(s[3], 128) for s in w.segments]
+    desc = gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, SUBBAND_GROUP)
+    dmt = torch.empty(desc.total, dtype=torch.int32, device="cuda:0")
+
+    def step():
+        ctx.dedisperse_subband(fb, w.freqs, desc, n_sub, SUBBAND_GROUP, out=dmt, stream=stream)
+        c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold, stream=stream)
+        return c, gsp.group_candidates(c)[1]
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    ctx.profile_read(reset=True)
+    t = time.perf_counter()
+    for _ in range(steps):
+        c, ng = step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / steps
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    work = sum(desc.seg[s].n_dm * desc.n_out[s] for s in range(desc.n_seg))
+    brute_adds = sum(desc.seg[s].n_dm * desc.n_out[s] * desc.nchan for s in range(desc.n_seg))
+    kernels = {k: {"ms_per_step": v[1] / steps, "avg_launch_ms": v[1] / v[0],
+                   "adds_per_s" if k.startswith("subband") else "bytes_per_s": v[2] / (v[1] / 1e3)}
+               for k, v in prof.items()}
+    ded_s = sum(prof[k][1] for k in ("subband1", "subband2", "stage") if k in prof) / steps / 1e3
+    del dmt
+    return {"n_sub": n_sub, "group": SUBBAND_GROUP, "ms_per_step": wall * 1e3, "value": work / wall,
+            "rtf": (w.nsamp * w.tsamp) / wall, "candidates": int(len(c)), "events": int(ng),
+            "dedispersion_ms": ded_s * 1e3,
+            "brute_force_equivalent_adds_per_s": brute_adds / ded_s,
+            "kernels": kernels,
+            "what": "sub-band dedispersion (stage 1: nchan/group adds per output, stage 2: n_sub) + statistics + "
+                    "search + grouping; an approximation of brute force judged by the injected pulses' SNR in "
+                    "the tests"}
 
 
 SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8, 4, 32), (2, 8, 8, 32),
@@ -259,6 +335,13 @@ def main():
                     help="comma-separated plan rows to keep (e.g. 0 for the D = 1 row alone; profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
+    ap.add_argument("--e2e-steps", type=int, default=2, help="steps timed with the host-to-device copy included")
+    ap.add_argument("--no-subband", dest="subband", action="store_false",
+                    help="skip the sub-band dedispersion measurement")
+    ap.add_argument("--no-stream", dest="stream_in_line", action="store_false",
+                    help="skip the paced 19-beam streaming run reported under 'stream'")
+    ap.add_argument("--stream-line-blocks", type=int, default=12,
+                    help="blocks per beam of the streaming run in the default line (19 beams)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU only: the library has no multi-GPU path (beams or DM ranges would shard "
@@ -382,11 +465,45 @@ def main():
                     "initialisation: timing only) + logits to host",
             "plain_ms_per_step": ms - t_triage[0] / args.steps * 1e3},
     }
+    out["native_dm_trial_samples_per_s"] = sum(desc.seg[r].n_dm * desc.n_out[r] * desc.seg[r].downsamp
+                                               for r in range(desc.n_seg)) / (ms / 1e3)
+    # end to end: the same step with the input copied from pinned host memory
+    # first (PCIe) and the candidates brought back (as every step does)
+    if args.e2e_steps > 0:
+        Xp = torch.from_numpy(X).pin_memory()
+        fb.copy_(Xp, non_blocking=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.e2e_steps):
+            fb.copy_(Xp, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d = (time.perf_counter() - t) / args.e2e_steps
+        t = time.perf_counter()
+        for _ in range(args.e2e_steps):
+            fb.copy_(Xp, non_blocking=True)
+            step()
+        torch.cuda.synchronize()
+        e2e = (time.perf_counter() - t) / args.e2e_steps
+        del Xp
+        out["end_to_end"] = {"ms_per_step": e2e * 1e3, "value": cfg["dm_trial_samples"] / e2e,
+                             "rtf": (w.nsamp * w.tsamp) / e2e, "h2d_ms": h2d * 1e3,
+                             "h2d_GBps": w.nsamp * w.nchan / h2d / 1e9, "steps": args.e2e_steps,
+                             "what": "host-to-device copy of the uint8 input from pinned memory + the step "
+                                     "(candidates to the host included)"}
+    if args.subband:
+        out["subband"] = bench_subband(ctx, w, fb, stream, args.steps)
+    del dmt
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, X, desc, args.cpu_every)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    del fb
+    torch.cuda.empty_cache()
+    if args.stream_in_line:
+        log("stream: 19 beams, paced, network attached (random weights: timing only) ...")
+        out["stream"] = bench_stream(True, max_blocks=args.stream_line_blocks, triage="random")
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

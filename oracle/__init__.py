@@ -59,6 +59,8 @@ def lib():
         P = C.c_void_p
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_fref.restype = C.c_double
         L.orc_fref.argtypes = [P, C.c_int32]
         L.orc_trial_dm.restype = C.c_double
@@ -115,6 +117,11 @@ def _seg(s) -> Seg:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timings)."""
+    lib().orc_set_threads(int(n))
 
 
 def fref(freqs) -> float:

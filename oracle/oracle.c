@@ -42,6 +42,9 @@
 /* Threads an OpenMP loop of the oracle uses (reported with CPU timings). */
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+/* Threads for later OpenMP loops (timings on fewer cores). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 typedef struct {
   double dm_lo;
   double dm_step;
