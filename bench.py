@@ -55,7 +55,7 @@ def describe(w, desc):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_realistic_traffic.md")
-DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", f) for f in ("dedisp_tile.h", "dedisp.hip")]
+DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_tile.h")]  # the kernel's device code
 
 
 def kernel_source_hash() -> str:
