@@ -336,6 +336,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy kernel (reference for hardware byte counters)")
     ap.add_argument("--e2e-steps", type=int, default=2, help="steps timed with the host-to-device copy included")
+    ap.add_argument("--rfi", action="store_true",
+                    help="clip outlying zero-DM spectra (blocks of 2048) and apply the zero-DM filter inside the step")
+    ap.add_argument("--clip-sigma", type=float, default=6.0)
     ap.add_argument("--no-subband", dest="subband", action="store_false",
                     help="skip the sub-band dedispersion measurement")
     ap.add_argument("--no-stream", dest="stream_in_line", action="store_false",
@@ -400,7 +403,14 @@ def main():
     logits = torch.empty(16384, dtype=torch.float32, device="cuda:0")
     t_triage = [0.0]
 
+    raw = None
+    if args.rfi:  # RFI mitigation inside the step: the raw input stays untouched, the cleaned copy is searched
+        raw = fb
+        fb = torch.empty_like(raw)
+
     def step():
+        if raw is not None:
+            ctx.rfi_clean(raw, args.clip_sigma, 2048, zero_dm=True, out=fb, count=False, stream=stream)
         ctx.dedisperse(fb, w.freqs, desc, out=dmt, stream=stream)
         c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold, stream=stream)
         rep, ng = gsp.group_candidates(c)
@@ -437,6 +447,8 @@ def main():
     ms = wall / args.steps * 1e3
     cfg = describe(w, desc)
     cfg["tile_shapes"] = [list(ctx.row_shape(w.freqs, desc, r)) for r in range(desc.n_seg)]
+    cfg["rfi_mitigation"] = (f"clip {args.clip_sigma:g} sigma in blocks of 2048 spectra + zero-DM filter" if args.rfi
+                             else None)
     cfg["autotuned"] = shapes is not None
     value = cfg["dm_trial_samples"] / (ms / 1e3)
     rtf = (w.nsamp * w.tsamp) / (ms / 1e3)
@@ -471,16 +483,17 @@ def main():
     # first (PCIe) and the candidates brought back (as every step does)
     if args.e2e_steps > 0:
         Xp = torch.from_numpy(X).pin_memory()
-        fb.copy_(Xp, non_blocking=True)
+        dst = raw if raw is not None else fb  # where the input lands
+        dst.copy_(Xp, non_blocking=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.e2e_steps):
-            fb.copy_(Xp, non_blocking=True)
+            dst.copy_(Xp, non_blocking=True)
         torch.cuda.synchronize()
         h2d = (time.perf_counter() - t) / args.e2e_steps
         t = time.perf_counter()
         for _ in range(args.e2e_steps):
-            fb.copy_(Xp, non_blocking=True)
+            dst.copy_(Xp, non_blocking=True)
             step()
         torch.cuda.synchronize()
         e2e = (time.perf_counter() - t) / args.e2e_steps
@@ -499,6 +512,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, X, desc, args.cpu_every)
     ctx.close()
     del fb
+    raw = None
     torch.cuda.empty_cache()
     if args.stream_in_line:
         log("stream: 19 beams, paced, network attached (random weights: timing only) ...")

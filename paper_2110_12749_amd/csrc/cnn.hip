@@ -8,7 +8,7 @@
 //   loss: binary cross-entropy with logits (mean over the batch); Adam.
 // Every convolution and fully connected product, forward and backward
 // (activation and weight gradients), runs on one hand-written GEMM kernel
-// built on the gfx950 BF16 matrix cores (v_mfma_f32_32x32x8bf16_1k), fed by
+// built on the gfx950 BF16 matrix cores (v_mfma_f32_32x32x16_bf16), fed by
 // im2col / col2im gathers; the epilogue fuses bias, ReLU and gradient masks.
 #include <cmath>
 #include <cstring>
@@ -18,7 +18,7 @@
 
 namespace gsp {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // --- bf16 helpers (round to nearest even) ---
@@ -45,7 +45,7 @@ __host__ __device__ inline float bf2f(uint16_t h) {
 // ---------------------------------------------------------------------------
 // GEMM: C[m][n] = sum_k A[m][k] B[k][n] (+ bias[n]) (ReLU) (mask) with
 // arbitrary element strides, BF16 inputs, FP32 accumulation.
-// Workgroup tile 64 x 64, k step 16; 4 waves, each a 32 x 32 MFMA tile.
+// Workgroup tile 64 x 64, k step 32 (two 32 x 32 x 16 MFMAs per wave); 4 waves, each a 32 x 32 tile.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   const uint16_t *A;
@@ -172,11 +172,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       pb = load_b(k0 + kTK);
     }
 #pragma unroll
-    for (int ks = 0; ks < kTK; ks += 8) {
-      const int kk = ks + (lane >> 5) * 4;
-      const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&As[wm + (lane & 31)][kk]);
-      const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Bt[wn + (lane & 31)][kk]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int ks = 0; ks < kTK; ks += 16) {
+      // 32 x 32 x 16: lane l holds row l % 32, k = 8 * (l / 32) .. + 7 of each operand
+      const int kk = ks + (lane >> 5) * 8;
+      const u16x8 a = *reinterpret_cast<const u16x8 *>(&As[wm + (lane & 31)][kk]);
+      const u16x8 b = *reinterpret_cast<const u16x8 *>(&Bt[wn + (lane & 31)][kk]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc,
+                                                     0, 0, 0);
     }
   }
   // epilogue: lane holds column wn + lane%32, rows 8*(j/4) + 4*(lane/32) + j%4

@@ -223,7 +223,8 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
 }
 
 void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_t D, int64_t N, int64_t n_out,
-                              int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread) {
+                              int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread,
+                              int64_t lds_budget) {
   struct {
     int32_t n_dm, downsamp;
   } g{n_dm, D};
@@ -267,15 +268,15 @@ void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_
   rt.row_dwords = widest;
   // staging passes over consecutive channels (neighbouring frequencies,
   // similar spreads): each as long as its staged copies fit the LDS budget
-  // left after the offsets and bases of the longest allowed pass, the
+  // left after the staging bases of the longest allowed pass, the
   // staging registers (`units` per thread) hold it, and at most the
   // requested number of channels
   const int threads = 64 * shape.waves;
   const int units = units_per_thread > 0 ? units_per_thread : unit_max_for_d(g.downsamp);
-  const int64_t kmax = std::min<int64_t>({(int64_t)shape.chunk, (int64_t)kOffMax * threads / MT, (int64_t)threads});
+  const int64_t kmax = std::min<int64_t>({(int64_t)shape.chunk, (int64_t)kPassMax, (int64_t)threads});
   if (kmax < 1) fail(GSP_EINVAL, "unsupported dedispersion shape");
-  const int64_t side = kmax * ((int64_t)MT * 4 + 8);  // offsets + two bases per channel, bytes
-  const int64_t data_budget = kLdsBudget - side;
+  const int64_t side = kmax * 8;  // two staging bases per channel, bytes
+  const int64_t data_budget = (lds_budget > 0 ? lds_budget : kLdsBudget) - side;
   std::vector<int32_t> passes;  // start, row dwords pairs
   int64_t data_dw = 0;
   int max_chunk = 0;
@@ -307,7 +308,7 @@ void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_
   rt.max_chunk = max_chunk;
   rt.data_dw = (int32_t)data_dw;
   rt.shape.chunk = max_chunk;
-  rt.lds_bytes = data_dw * 4 + (int64_t)max_chunk * ((int64_t)MT * 4 + 8);
+  rt.lds_bytes = data_dw * 4 + (int64_t)max_chunk * 8;
   if (rt.lds_bytes > kLdsMax) fail(GSP_EINVAL, "dedispersion tile does not fit in LDS (delay spread too wide)");
   std::vector<uint32_t> addr((size_t)nchan * n_dm_pad);
   for (size_t q = 0; q + 2 < passes.size(); q += 2) {

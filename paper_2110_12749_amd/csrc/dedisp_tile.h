@@ -40,12 +40,13 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 // Staging unit: 16 consecutive samples of one channel, i.e. 8 dwords of each
 // LDS copy.  Per pass each thread stages at most unit_max units (uint8
 // sources: 3; uint16 sources, 9 registers a unit: 2, which keeps 4 waves per
-// SIMD) and kOffMax trial offsets (two, loaded and stored as one 8-byte
-// pair).  Longer passes mean fewer workgroup barriers per channel.
+// SIMD).  Longer passes mean fewer workgroup barriers per channel.  The trial
+// offsets of a pass live in registers, one channel per lane, so a pass has
+// at most kPassMax channels.
 template <typename SrcT>
 constexpr int unit_max() { return sizeof(SrcT) == 1 ? 3 : 2; }
 constexpr int unit_max_for_d(int D) { return D == 1 ? 3 : 2; }
-static constexpr int kOffMax = 2;
+static constexpr int kPassMax = 64;
 
 template <typename SrcT>
 struct Unit {
@@ -73,10 +74,10 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
   const int i_tile = dm_tile * MT;
   const int n_chunks = a.n_chunks;
   const int maxc = a.max_chunk;
-  // LDS: samples [pass channels][2][row dwords] | offsets [max_chunk][MT] | staging bases [2][max_chunk]
+  // LDS: samples [pass channels][2][row dwords] | staging bases [2][max_chunk]
   uint32_t *data = lds;
-  uint32_t *offs = lds + a.data_dw;
-  int32_t *bases = reinterpret_cast<int32_t *>(offs + maxc * MT);
+  int32_t *bases = reinterpret_cast<int32_t *>(lds + a.data_dw);
+  const int i_wave = i_tile + wave * TPW;  // this wave's first trial
   // the pass table is read 64 passes at a time into one register per lane
   // (lane l: pass w0 + l) and taken with readlane, so no scalar load (whose
   // wait would also drain the LDS queue) sits in the pass loop
@@ -97,7 +98,12 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
 
   // ---- staging helpers ----
   Unit<SrcT> pu[unit_max<SrcT>()];
-  uint2 poff = make_uint2(0, 0);
+  // trial offsets of the wave's TPW trials: lane l holds channel l of the
+  // pass (roff: the pass being summed, noff: the next one, in flight); the
+  // sums read them with readlane, so they cost no LDS traffic
+  uint32_t roff[TPW], noff[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) noff[j] = 0;
   auto prefetch = [&](int j) {  // global -> registers for pass j (bases of j already in LDS)
     const int cs = ch_begin(j), ce = ch_begin(j + 1);
     const int U = row_dw_of(j) >> 3;  // staging units per channel
@@ -123,10 +129,16 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       pu[i].tail = rows[i][16];
     }
     {
-      // offsets 2 tid and 2 tid + 1 of the pass (same channel: MT is even)
-      const int q = 2 * tid;
-      if (q < (ce - cs) * MT)
-        poff = *reinterpret_cast<const uint2 *>(a.addr + (int64_t)(cs + q / MT) * a.n_dm_pad + i_tile + q % MT);
+      // offsets of the wave's trials at channel cs + lane (clamped into the pass)
+      const uint32_t *src = a.addr + (int64_t)(cs + min(lane, ce - cs - 1)) * a.n_dm_pad + i_wave;
+#pragma unroll
+      for (int j = 0; j < TPW; j += 4) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(src + j);
+        noff[j] = q.x;
+        noff[j + 1] = q.y;
+        noff[j + 2] = q.z;
+        noff[j + 3] = q.w;
+      }
     }
   };
   auto store = [&](int j) {  // registers -> LDS for pass j
@@ -174,10 +186,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
         d1[1] = make_uint4(c1[4], c1[5], c1[6], c1[7]);
       }
     }
-    {
-      const int q = 2 * tid;
-      if (q < (ce - cs) * MT) *reinterpret_cast<uint2 *>(offs + q) = poff;
-    }
   };
 
   // ---- accumulators ----
@@ -209,15 +217,9 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
         }
     }
   };
-  auto load_off = [&](const uint32_t *p, uint32_t *o) {
+  auto load_off = [&](int c, uint32_t *o) {  // offsets of channel c of the pass (c uniform)
 #pragma unroll
-    for (int j = 0; j < TPW; j += 4) {
-      const uint4 q = *reinterpret_cast<const uint4 *>(p + j);
-      o[j] = q.x;
-      o[j + 1] = q.y;
-      o[j + 2] = q.z;
-      o[j + 3] = q.w;
-    }
+    for (int j = 0; j < TPW; ++j) o[j] = (uint32_t)__builtin_amdgcn_readlane((int)roff[j], c);
   };
   auto load_v = [&](const uint32_t *o, uint32_t (*dst)[K]) {
 #pragma unroll
@@ -245,26 +247,26 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
     // in flight during the accumulation below: samples of pass kc+1, bases of kc+2
     if (kc + 2 < n_chunks)
       pbase = tid < ch_begin(kc + 3) - ch_begin(kc + 2) ? base_row[ch_begin(kc + 2) + tid] : 0;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) roff[j] = noff[j];  // loaded with pass kc's samples
     if (kc + 1 < n_chunks) prefetch(kc + 1);
 
     // ---- accumulate pass kc: per channel TPW trials x K dwords per lane ----
     // two register sets: while one channel is added, the next one's samples
-    // and the one after's offsets are in flight (LDS returns in order).  The
-    // loads are unconditional (channel index clamped to the pass) so that no
-    // branch forces a full wait before the adds.
-    const uint32_t *orow = offs + wave * TPW;
+    // are in flight.  The loads are unconditional (channel index clamped to
+    // the pass) so that no branch forces a full wait before the adds.
     const int last = ce - 1 - cs;
     uint32_t offA[TPW], offB[TPW], vA[TPW][K], vB[TPW][K];
-    load_off(orow, offA);
+    load_off(0, offA);
     load_v(offA, vA);
-    load_off(orow + min(1, last) * MT, offB);
+    load_off(min(1, last), offB);
     for (int c = 0; c <= last; c += 2) {
       load_v(offB, vB);
-      load_off(orow + min(c + 2, last) * MT, offA);
+      load_off(min(c + 2, last), offA);
       add_flush(vA);
       if (c + 1 > last) break;
       load_v(offA, vA);
-      load_off(orow + min(c + 3, last) * MT, offB);
+      load_off(min(c + 3, last), offB);
       add_flush(vB);
     }
   }
@@ -276,7 +278,6 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       tot[j][k][1] += (int32_t)(acc[j][k] >> 16);
     }
   // ---- store ----
-  const int i_wave = i_tile + wave * TPW;
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int i = i_wave + j;

@@ -278,8 +278,9 @@ SubbandPlan &subband_plan(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *
           rt->delays_host[(size_t)(i - i0) * R->n_sub + b] = v;
           mx = std::max<int64_t>(mx, v);
         }
+      // LDS for as many workgroups of waves2 waves as fill a CU's 16 wave slots
       build_tables_from_delays(ctx, i1 - i0, R->n_sub, g.downsamp, R->Zn, R->n_out, mx, sh2, *rt,
-                               unit_max<uint16_t>());
+                               unit_max<uint16_t>(), (int64_t)160 * 1024 * R->waves2 / 16);
       zp = std::max(zp, staged_pitch(*rt));
       R->s2.push_back(std::move(rt));
     }
