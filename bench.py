@@ -31,6 +31,9 @@ PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 VALU
 # The dedispersion kernel adds two 16-bit sample sums per 32-bit add, so the
 # ceiling of its instruction mix, in sample additions, is twice the int32 rate.
 PEAK_SAMPLE_ADDS = 2 * PEAK_INT32_OPS
+# LDS read rates measured on the MI355X for the kernel's access pattern, B/clk/CU
+LDS_READ2ST64 = 110.2  # ds_read2st64_b32, offsets from registers (the kernel's form)
+LDS_B128 = 176.7       # ds_read_b128 at 16-byte aligned addresses
 
 
 def log(*a):
@@ -225,8 +228,23 @@ def bench_stream(paced: bool, pool_blocks: int = 24, max_blocks: int | None = No
                 "ms_per_block": rep["triage_s"] / max(1, rep["blocks"]) * 1e3}}
 
 
-SUBBAND_NSUB = {1: 64, 2: 64, 4: 64, 8: 128}  # bands per row by downsampling (16-bit sub-band series)
-SUBBAND_GROUP = 16
+# bands per row by downsampling (16-bit sub-band series: 255 * D * channels per
+# band <= 65535) and trials per group; chosen by a sweep on the realistic
+# workload (step time against the injected pulses' SNR relative to brute force)
+SUBBAND_NSUB = {1: 32, 2: 32, 4: 64, 8: 128}
+SUBBAND_GROUP = 32  # at most this many trials per group
+
+
+def subband_groups(segments, gmax=SUBBAND_GROUP, tile=32):
+    """Per row, the smallest group size that needs no more stage-1 tiles of
+    `tile` groups than groups of gmax would (so no tile is padded more than
+    needed): e.g. 1500 trials -> 24 (63 groups in 2 tiles), 600 -> 19."""
+    out = []
+    for s in segments:
+        n_dm = s[2]
+        tiles = -(-n_dm // (tile * gmax))
+        out.append(-(-n_dm // (tile * tiles)))
+    return out
 
 
 def bench_subband(ctx, w, fb, stream, steps):
@@ -235,11 +253,12 @@ def bench_subband(ctx, w, fb, stream, steps):
     import torch
     from paper_2110_12749_amd import gsp
     n_sub = [SUBBAND_NSUB.get(s[3], 128) for s in w.segments]
-    desc = gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, SUBBAND_GROUP)
+    group = subband_groups(w.segments)
+    desc = gsp.subband_plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments, n_sub, group)
     dmt = torch.empty(desc.total, dtype=torch.int32, device="cuda:0")
 
     def step():
-        ctx.dedisperse_subband(fb, w.freqs, desc, n_sub, SUBBAND_GROUP, out=dmt, stream=stream)
+        ctx.dedisperse_subband(fb, w.freqs, desc, n_sub, group, out=dmt, stream=stream)
         c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold, stream=stream)
         return c, gsp.group_candidates(c)[1]
 
@@ -262,7 +281,7 @@ def bench_subband(ctx, w, fb, stream, steps):
                for k, v in prof.items()}
     ded_s = sum(prof[k][1] for k in ("subband1", "subband2", "stage") if k in prof) / steps / 1e3
     del dmt
-    return {"n_sub": n_sub, "group": SUBBAND_GROUP, "ms_per_step": wall * 1e3, "value": work / wall,
+    return {"n_sub": n_sub, "group": group, "ms_per_step": wall * 1e3, "value": work / wall,
             "rtf": (w.nsamp * w.tsamp) / wall, "candidates": int(len(c)), "events": int(ng),
             "dedispersion_ms": ded_s * 1e3,
             "brute_force_equivalent_adds_per_s": brute_adds / ded_s,
@@ -468,7 +487,17 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_dedisp", "work": "integer adds (n_dm * n_out * nchan per launch)",
                      "peak_note": "two 16-bit sample additions per packed 32-bit VALU add: 2 x 256 CUs x 64 lanes "
-                                  "x 2.4 GHz; the kernel's LDS reads bound it lower, at 32.8 T adds/s"},
+                                  "x 2.4 GHz; the kernel is bound by its LDS reads (see 'lds'), at about 34 T "
+                                  "adds/s with its read form"},
+        "lds": {"what": "LDS read bandwidth of the dedispersion kernel: 2 bytes of staged samples per sample add "
+                        "(one ds_read2st64_b32 of 512 bytes per 256 adds and wave)",
+                "achieved_TBps": 2.0 * achieved / 1e12,
+                "peak_form_TBps": LDS_READ2ST64 * 256 * 2.4e9 / 1e12,
+                "frac_form": 2.0 * achieved / (LDS_READ2ST64 * 256 * 2.4e9),
+                "peak_b128_TBps": LDS_B128 * 256 * 2.4e9 / 1e12,
+                "frac_b128": 2.0 * achieved / (LDS_B128 * 256 * 2.4e9),
+                "note": "measured on MI355X with this access pattern and the packed adds: ds_read2st64_b32 with "
+                        "register offsets 110.2 B/clk/CU, ds_read_b128 (16-byte aligned) 176.7 B/clk/CU"},
         "kernels": kernels,
         "candidates": int(len(c)), "events": int(ng),
         "triage": None if net is None else {

@@ -224,7 +224,7 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
 
 void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_t D, int64_t N, int64_t n_out,
                               int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread,
-                              int64_t lds_budget) {
+                              int64_t lds_budget, int32_t pass_break) {
   struct {
     int32_t n_dm, downsamp;
   } g{n_dm, D};
@@ -284,6 +284,7 @@ void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan_, int32_
     int k = 0;
     int32_t rd = 0;
     while (c + k < nchan) {
+      if (k > 0 && pass_break > 0 && (c + k) % pass_break == 0) break;  // output segment boundary
       const int32_t rd2 = std::max(rd, row_dw_c[c + k]);
       const int64_t k2 = k + 1;
       const bool fits = k2 <= kmax && 2 * k2 * rd2 * 4 <= data_budget && k2 * (rd2 / 8) <= (int64_t)units * threads;
@@ -376,6 +377,7 @@ static void launch_k(const DedispArgs &a, int waves, int64_t lds, int D, hipStre
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st) {
   const DedispShape &sh = rt.shape;
   DedispArgs a;
+  std::memset(&a, 0, sizeof(a));
   a.Y = ctx->staged.ptr;
   a.pitch = staged_pitch(rt);
   a.addr = rt.addr.as<uint32_t>();

@@ -27,6 +27,11 @@ struct DedispArgs {
   int32_t data_dw;          // LDS dwords of the largest pass's staged copies
   int32_t flush;            // channels between flushes of the 16-bit lanes
   int32_t n_dm_tiles, n_t_tiles;
+  // output segments (0: none): the sums of channels [s*seg_ch, (s+1)*seg_ch)
+  // go to out + s*seg_stride (elements), each segment's sums starting from
+  // zero; passes never straddle a segment boundary
+  int32_t seg_ch;
+  int64_t seg_stride;
 };
 
 __device__ __forceinline__ int xcd_remap(int b, int G) {
@@ -59,7 +64,9 @@ struct Unit {
 // t0 = t_origin + t_tile * 128*K.  Every thread of the workgroup calls it.
 // OutT: int32_t, or uint16_t where every sum is known to fit 16 bits (the
 // sub-band series of sub-band dedispersion).
-template <int K, int TPW, typename SrcT, typename OutT = int32_t>
+// SEG: the sums go to output segments of a.seg_ch channels (the sub-band
+// series of sub-band dedispersion); without it a.seg_ch is ignored.
+template <int K, int TPW, typename SrcT, typename OutT = int32_t, bool SEG = false>
 __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, int t_tile, uint32_t *lds) {
   static_assert(TPW % 4 == 0, "offsets are read four trials at a time");
   const int tid = threadIdx.x;
@@ -230,6 +237,39 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
     }
   };
 
+  // fold the 16-bit lanes into the totals, store the sums of output
+  // segment `seg`, and start the next segment from zero
+  auto finish = [&](int seg) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        tot[j][k][0] += (int32_t)(acc[j][k] & 0xFFFFu);
+        tot[j][k][1] += (int32_t)(acc[j][k] >> 16);
+        acc[j][k] = 0;
+      }
+    since_flush = 0;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const int i = i_wave + j;
+      if (i >= a.n_dm) break;
+      OutT *orow_out = static_cast<OutT *>(a.out) + (int64_t)seg * a.seg_stride + (int64_t)i * a.out_pitch - a.t_lo;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
+        if (t >= a.t_lo && t < a.t_hi) orow_out[t] = (OutT)tot[j][k][0];
+        if (t + 1 >= a.t_lo && t + 1 < a.t_hi) orow_out[t + 1] = (OutT)tot[j][k][1];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        tot[j][k][0] = 0;
+        tot[j][k][1] = 0;
+      }
+  };
+
   // ---- prologue: bases of passes 0 (LDS) and 1 (register), samples of pass 0 ----
   // (a pass has at most max_chunk <= threads channels: one base per thread)
   if (tid < ch_begin(1) - ch_begin(0)) bases[tid] = base_row[ch_begin(0) + tid];
@@ -269,27 +309,11 @@ __device__ __forceinline__ void dedisp_tile(const DedispArgs &a, int dm_tile, in
       load_off(min(c + 3, last), offB);
       add_flush(vB);
     }
-  }
-#pragma unroll
-  for (int j = 0; j < TPW; ++j)
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      tot[j][k][0] += (int32_t)(acc[j][k] & 0xFFFFu);
-      tot[j][k][1] += (int32_t)(acc[j][k] >> 16);
-    }
-  // ---- store ----
-#pragma unroll
-  for (int j = 0; j < TPW; ++j) {
-    const int i = i_wave + j;
-    if (i >= a.n_dm) break;
-    OutT *orow_out = static_cast<OutT *>(a.out) + (int64_t)i * a.out_pitch - a.t_lo;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
-      if (t >= a.t_lo && t < a.t_hi) orow_out[t] = (OutT)tot[j][k][0];
-      if (t + 1 >= a.t_lo && t + 1 < a.t_hi) orow_out[t + 1] = (OutT)tot[j][k][1];
+    if constexpr (SEG) {
+      if (kc + 1 < n_chunks && ce % a.seg_ch == 0) finish(ce / a.seg_ch - 1);
     }
   }
+  finish(SEG ? (a.nchan - 1) / a.seg_ch : 0);
 }
 
 // Batch launch: one tile per workgroup, XCD-aware tile order.

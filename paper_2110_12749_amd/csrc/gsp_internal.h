@@ -188,9 +188,11 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
 // (delays of D*tsamp samples, max_delay their largest; n_out outputs).
 // lds_budget > 0: LDS bytes per workgroup the staging passes may use (default
 // 80 KB: two workgroups per CU)
+// pass_break > 0: no staging pass straddles a multiple of pass_break channels
+// (segmented outputs, DedispArgs::seg_ch)
 void build_tables_from_delays(gsp_ctx *ctx, int32_t n_dm, int32_t nchan, int32_t D, int64_t N, int64_t n_out,
                               int64_t max_delay, const DedispShape &shape, RowTables &rt, int units_per_thread = 0,
-                              int64_t lds_budget = 0);
+                              int64_t lds_budget = 0, int32_t pass_break = 0);
 // pitch_override > 0: stage with that pitch (elements per channel row, a
 // multiple of 256 covering every read of the kernels that use the copy)
 void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const RowTables &rt, hipStream_t st,

@@ -587,6 +587,8 @@ int64_t step_once(gsp_stream *s) {
       DedispJob &D = td.job[td.n_jobs++];
       const RowTables &rt = R.tables;
       DedispArgs &A = D.a;
+      A.seg_ch = 0;  // one output for all channels
+      A.seg_stride = 0;
       const int64_t origin = a & ~int64_t(3);
       A.Y = R.ring.ptr;
       A.pitch = R.R + kGuard;

@@ -64,7 +64,7 @@ __device__ __forceinline__ int sub_find(const SubTable *t, int64_t b) {
 // Persistent grid over the tiles of every job; with a multiple of 8
 // workgroups each XCD takes a contiguous eighth of the tiles (neighbouring
 // tiles share their input windows in that XCD's L2).
-template <int K, int TPW, typename SrcT, typename OutT>
+template <int K, int TPW, typename SrcT, typename OutT, bool SEG>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_dedisp_sub(
     const SubTable *__restrict__ tb, const char *src_base, char *dst_base) {
   extern __shared__ uint32_t lds[];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     a.out = dst_base + reinterpret_cast<intptr_t>(a.out);
     const int64_t local = b - tb->job[j].item0;
     __syncthreads();  // LDS of the previous tile is free
-    dedisp_tile<K, TPW, SrcT, OutT>(a, (int)(local % a.n_dm_tiles), (int)(local / a.n_dm_tiles), lds);
+    dedisp_tile<K, TPW, SrcT, OutT, SEG>(a, (int)(local % a.n_dm_tiles), (int)(local / a.n_dm_tiles), lds);
   }
 }
 
@@ -95,6 +95,7 @@ struct SubChunk {
   DevBuf t1, t2;                                  // job tables of the two stages
   int64_t lds1 = 0, lds2 = 0;
   double adds1 = 0, adds2 = 0;
+  bool seg = false;  // stage 1 is one job with band segments
 };
 
 struct SubRow {
@@ -302,6 +303,25 @@ SubbandPlan &subband_plan(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *
       C->g0 = ga;
       C->g1 = std::min(R->n_groups, ga + gc);
       const int32_t ng = C->g1 - C->g0;
+      if (nchan % R->n_sub == 0) {
+        // equal bands: one job over every channel of the row, the sums of
+        // each band stored as an output segment of its own
+        const int32_t cpb = nchan / R->n_sub;
+        auto rt = std::make_unique<RowTables>();
+        rt->delays_host.resize((size_t)ng * nchan);
+        int64_t mx = 0;
+        for (int32_t q = 0; q < ng; ++q)
+          for (int32_t c = 0; c < nchan; ++c) {
+            const int32_t v = d1[(size_t)(C->g0 + q) * nchan + c];
+            rt->delays_host[(size_t)q * nchan + c] = v;
+            mx = std::max<int64_t>(mx, v);
+          }
+        build_tables_from_delays(ctx, ng, nchan, g.downsamp, R->N, R->Zn, mx, sh1, *rt, 0, 0, cpb);
+        pitch = std::max(pitch, staged_pitch(*rt));
+        C->s1.push_back(std::move(rt));
+        R->chunks.push_back(std::move(C));
+        continue;
+      }
       for (int32_t b = 0; b < R->n_sub; ++b) {
         const int32_t cb = R->c0[b], ce = R->c0[b + 1];
         auto rt = std::make_unique<RowTables>();
@@ -325,7 +345,20 @@ SubbandPlan &subband_plan(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *
     for (auto &Cp : R->chunks) {
       SubChunk &C = *Cp;
       std::vector<SubJob> j1, j2;
-      for (int32_t b = 0; b < R->n_sub; ++b) {
+      if (C.s1.size() == 1 && R->n_sub > 1) {  // one segmented job over the row
+        const RowTables &rt = *C.s1[0];
+        SubJob J;
+        J.a = job_args(rt, 0, R->pitch, 0, (int64_t)R->n_sub * R->Zpitch, R->Zn,
+                       std::max(1, std::min(65535 / (255 * R->D), 256)));
+        J.a.seg_ch = nchan / R->n_sub;
+        J.a.seg_stride = R->Zpitch;
+        C.seg = true;
+        J.item0 = 0;
+        j1.push_back(J);
+        C.lds1 = std::max(C.lds1, rt.lds_bytes);
+        C.adds1 += (double)rt.n_dm * (double)R->Zn * (double)rt.nchan;
+      }
+      for (int32_t b = 0; b < R->n_sub && !(C.s1.size() == 1 && R->n_sub > 1); ++b) {
         const RowTables &rt = *C.s1[b];
         SubJob J;
         J.a = job_args(rt, (int64_t)R->c0[b] * R->pitch * (int64_t)elem, R->pitch,
@@ -358,9 +391,9 @@ SubbandPlan &subband_plan(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *
   return *slot;
 }
 
-template <typename SrcT, typename OutT>
+template <typename SrcT, typename OutT, bool SEG = false>
 void launch_sub(const DevBuf &table, int waves, int64_t lds, const void *src, void *dst, hipStream_t st) {
-  auto kern = k_dedisp_sub<kSubK, kSubTpw, SrcT, OutT>;
+  auto kern = k_dedisp_sub<kSubK, kSubTpw, SrcT, OutT, SEG>;
   check_hip(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
             "set LDS size");
   hipLaunchKernelGGL(kern, dim3(256 * 2), dim3(64 * waves), (size_t)lds, st, table.as<SubTable>(),
@@ -408,8 +441,13 @@ void dedisperse_subband(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, co
       SubChunk &C = *Cp;
       {
         ProfScope prof(ctx, "subband1", st, C.adds1);
-        if (R.D == 1)
+        const bool seg = C.seg;  // one job over the row with band segments
+        if (R.D == 1 && seg)
+          launch_sub<uint8_t, uint16_t, true>(C.t1, 8, C.lds1, ctx->staged.ptr, ctx->zbuf.ptr, st);
+        else if (R.D == 1)
           launch_sub<uint8_t, uint16_t>(C.t1, 8, C.lds1, ctx->staged.ptr, ctx->zbuf.ptr, st);
+        else if (seg)
+          launch_sub<uint16_t, uint16_t, true>(C.t1, 8, C.lds1, ctx->staged.ptr, ctx->zbuf.ptr, st);
         else
           launch_sub<uint16_t, uint16_t>(C.t1, 8, C.lds1, ctx->staged.ptr, ctx->zbuf.ptr, st);
       }

@@ -12,7 +12,7 @@ representative the network accepts:
     recall  = injected pulses with at least one matching passed event / pulses,
     events  = number of events passed on.
 
-Run: python -m paper_2110_12749_amd.triage --train-beams 60 --test-beams 30
+Run: python -m paper_2110_12749_amd.triage   (defaults: 40 training, 12 validation, 30 test beams)
 (one JSON line on stdout).
 """
 from __future__ import annotations
@@ -171,12 +171,12 @@ def recall_and_events(beams_scores, tau: float | None) -> tuple:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-beams", type=int, default=60)
-    ap.add_argument("--val-beams", type=int, default=16)
+    ap.add_argument("--train-beams", type=int, default=40)
+    ap.add_argument("--val-beams", type=int, default=12)
     ap.add_argument("--test-beams", type=int, default=30)
     ap.add_argument("--per-event", type=int, default=16)
     ap.add_argument("--per-pulse", type=int, default=256)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
