@@ -292,7 +292,10 @@ def bench_subband(ctx, w, fb, stream, steps):
 
 
 SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8, 4, 32), (2, 8, 8, 32),
-                (8, 4, 8, 32)]
+                (8, 4, 8, 32),
+                # byte-quad tile (D = 1 rows with whole channel quads)
+                (8, 4, 8, 64, 1), (8, 4, 16, 64, 1), (8, 2, 16, 64, 1), (4, 8, 8, 64, 1), (16, 2, 16, 64, 1),
+                (4, 4, 16, 64, 1), (4, 8, 16, 64, 1), (4, 8, 4, 64, 1)]
 
 
 def shape_sweep(w):
@@ -306,7 +309,7 @@ def shape_sweep(w):
     fb = torch.from_numpy(X).to("cuda:0")
     del X
     ctx = gsp.Context(0)
-    print(f"| row | D | n_dm | requested (groups, tpw, waves, chunk) | used | ms | T adds/s |")
+    print(f"| row | D | n_dm | requested (groups, tpw, waves, chunk[, kind]) | used | ms | T adds/s |")
     print("|---|---|---|---|---|---|---|")
     for s, seg in enumerate(w.segments):
         d1 = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, [seg])

@@ -412,18 +412,26 @@ int gsp_stream_set_graph(gsp_stream *s, int enable);
 int gsp_stream_set_fragment_capacity(gsp_stream *s, int64_t cap);
 
 /* Launch shape of the dedispersion kernel for one plan row: each workgroup
- * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials
- * over 128*`groups` output samples; at most `chunk` channels are staged into
- * LDS per pass.  Passes run over consecutive channels and each is as long as
- * the LDS budget, the staging registers and the trial offsets a thread loads
- * allow for the staged windows of its channels (a channel's window covers
- * the delay spread of a tile of trials at that channel), up to `chunk`.
- * gsp_row_shape reports the longest pass in `chunk`. */
+ * holds `waves` wavefronts of 64 lanes; a wave accumulates `tpw` DM trials.
+ * kind 0, the 16-bit tile (any row): a wave covers 128*`groups` output
+ * samples (dwords of two 16-bit samples); at most `chunk` channels are
+ * staged into LDS per pass.  Passes run over consecutive channels and each
+ * is as long as the LDS budget, the staging registers and the trial offsets
+ * a thread loads allow for the staged windows of its channels (a channel's
+ * window covers the delay spread of a tile of trials at that channel), up
+ * to `chunk`.  kind 1, the byte-quad tile (rows with D = 1 and a multiple of
+ * 4 channels): a wave covers 64*`groups` output samples; LDS dwords hold the
+ * bytes of 4 neighbouring channels, one staged copy per distinct pattern of
+ * delay differences inside the quad over a tile of trials; at most `chunk`
+ * (<= 64) quads per pass.  The default is kind 1 where it applies and its
+ * copies fit, else kind 0.  gsp_row_shape reports the longest pass in
+ * `chunk`. */
 typedef struct gsp_shape {
-  int32_t groups; /* 2, 4 or 8 */
-  int32_t tpw;    /* 4 or 8 */
-  int32_t waves;  /* 1 .. 8 */
+  int32_t groups; /* kind 0: 2, 4 or 8; kind 1: 4, 8 or 16 */
+  int32_t tpw;    /* kind 0: 4 or 8; kind 1: 2, 4 or 8 */
+  int32_t waves;  /* kind 0: 1 .. 8; kind 1: 1 .. 16 */
   int32_t chunk;  /* >= 1 */
+  int32_t kind;   /* 0: 16-bit tile, 1: byte-quad tile */
 } gsp_shape;
 
 /* Autotuner.  For every plan row of `desc`, times the dedispersion kernel
@@ -439,8 +447,9 @@ int gsp_row_shape(gsp_ctx *ctx, const double *freqs_mhz, const gsp_dmt_desc *des
 /* Force a shape for rows with the signature of row `seg` (tests, tuning). */
 int gsp_set_row_shape(gsp_ctx *ctx, const double *freqs_mhz, const gsp_dmt_desc *desc, int32_t seg,
                       const gsp_shape *shape);
-/* Tuned shapes as text, one "signature groups tpw waves chunk" line per row
- * signature; load merges into the context's table. */
+/* Tuned shapes as text, one "signature groups tpw waves chunk kind" line per
+ * row signature; load merges into the context's table (a missing kind reads
+ * as 0). */
 int gsp_tuning_save(const gsp_ctx *ctx, const char *path);
 int gsp_tuning_load(gsp_ctx *ctx, const char *path);
 

@@ -70,13 +70,29 @@ RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
   }
   auto &slot = it->second->rows[s];
   const DedispShape want = shape_for_row(ctx, desc, s);
-  if (slot && (slot->shape.groups != want.groups || slot->shape.tpw != want.tpw || slot->shape.waves != want.waves ||
-               slot->req_chunk != want.chunk))
+  const DedispShape had = slot ? slot->req : want;
+  if (slot && (had.groups != want.groups || had.tpw != want.tpw || had.waves != want.waves || had.kind != want.kind ||
+               had.chunk != want.chunk))
     slot.reset();  // the tuned shape changed since the tables were built
   if (!slot) {
     auto rt = std::make_unique<RowTables>();
-    build_row_tables(ctx, desc, freqs, s, want, *rt);
-    rt->req_chunk = want.chunk;
+    try {
+      build_row_tables(ctx, desc, freqs, s, want, *rt);
+    } catch (const Error &e) {
+      // the byte-quad default does not suit every row (delay spreads wider
+      // than its LDS copies): such rows keep the 16-bit tile
+      const bool tuned = ctx->tuned.count(row_signature(desc, s)) > 0;
+      if (e.status != GSP_EINVAL || want.kind != 1 || tuned) throw;
+      DedispShape pair = want;
+      pair.kind = 0;
+      pair.groups = 4;
+      pair.chunk = 32;
+      std::vector<int32_t> delays = std::move(rt->delays_host);
+      rt = std::make_unique<RowTables>();
+      rt->delays_host = std::move(delays);
+      build_row_tables(ctx, desc, freqs, s, pair, *rt);
+    }
+    rt->req = want;
     slot = std::move(rt);
   }
   return *slot;

@@ -164,17 +164,24 @@ namespace gsp {
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-DedispShape default_shape(int32_t D) {
+DedispShape default_shape(int32_t D, int32_t nchan) {
   DedispShape s;
   s.tpw = 4;
   s.waves = 8;
   s.groups = 4;
   s.chunk = 32;
-  (void)D;
+  if (D == 1 && nchan % 4 == 0) {  // byte-quad tile
+    s.kind = 1;
+    s.groups = 4;
+    s.tpw = 8;
+    s.chunk = 64;
+  }
   return s;
 }
 
 bool shape_supported(const DedispShape &s) {
+  if (s.kind == 1) return quad_shape_supported(s);
+  if (s.kind != 0) return false;
   const int kt = s.groups * 16 + s.tpw;
   const bool inst = kt == 8 * 16 + 4 || kt == 4 * 16 + 8 || kt == 4 * 16 + 4 || kt == 2 * 16 + 8;
   return inst && s.waves >= 1 && s.waves <= 8 && s.chunk >= 1;
@@ -190,7 +197,7 @@ std::string row_signature(const gsp_dmt_desc *desc, int32_t s) {
 
 DedispShape shape_for_row(gsp_ctx *ctx, const gsp_dmt_desc *desc, int32_t s) {
   auto it = ctx->tuned.find(row_signature(desc, s));
-  return it != ctx->tuned.end() ? it->second : default_shape(desc->seg[s].downsamp);
+  return it != ctx->tuned.end() ? it->second : default_shape(desc->seg[s].downsamp, desc->nchan);
 }
 
 static constexpr int64_t kLdsBudget = 80 * 1024;  // two workgroups per CU
@@ -203,6 +210,7 @@ static int flush_interval(int32_t D) {
 }
 
 int64_t staged_pitch(const RowTables &rt) {
+  if (rt.shape.kind == 1) return rt.q_pitch;
   // furthest element a staging pass can touch: t0 + base + 2 * row_dw + 2
   const int64_t T = rt.shape.samples_per_block();
   const int64_t n_t = (rt.n_out + T - 1) / T;
@@ -217,6 +225,17 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
   if (rt.delays_host.empty()) {
     rt.delays_host.resize((size_t)g.n_dm * desc->nchan);
     compute_delays(desc, freqs, s, rt.delays_host.data());
+  }
+  if (shape.kind == 1) {
+    rt.n_dm = g.n_dm;
+    rt.D = g.downsamp;
+    rt.nchan = desc->nchan;
+    rt.N = desc->nsamp / g.downsamp;
+    rt.n_out = desc->n_out[s];
+    rt.max_delay = desc->max_delay[s];
+    rt.shape = shape;
+    build_quad_tables(ctx, rt);
+    return;
   }
   build_tables_from_delays(ctx, g.n_dm, desc->nchan, g.downsamp, desc->nsamp / g.downsamp, desc->n_out[s],
                            desc->max_delay[s], shape, rt, units_per_thread);
@@ -375,6 +394,10 @@ static void launch_k(const DedispArgs &a, int waves, int64_t lds, int D, hipStre
 }
 
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st) {
+  if (rt.shape.kind == 1) {
+    launch_dedisp_quad(ctx, rt, out_row, st);
+    return;
+  }
   const DedispShape &sh = rt.shape;
   DedispArgs a;
   std::memset(&a, 0, sizeof(a));

@@ -40,9 +40,11 @@ struct DedispShape {
   int tpw = 4;       // trials per wave
   int waves = 8;     // waves per block
   int groups = 8;    // dword groups per lane (samples per block = 128 * groups)
-  int chunk = 32;    // channels staged per pass
+  int chunk = 32;    // channels staged per pass (kind 1: channel quads per pass)
+  int kind = 0;      // 0: 16-bit pair tile (any row); 1: byte-quad tile (D = 1, nchan % 4 == 0)
   int trials_per_block() const { return tpw * waves; }
-  int samples_per_block() const { return 128 * groups; }
+  // kind 0: a lane sums `groups` dwords of two samples; kind 1: `groups` dwords of one sample
+  int samples_per_block() const { return (kind == 1 ? 64 : 128) * groups; }
 };
 
 // Per-row device tables for one plan (cached by plan key).
@@ -52,7 +54,7 @@ struct RowTables {
   int64_t n_out = 0;
   int64_t max_delay = 0;
   DedispShape shape;
-  int32_t req_chunk = 0;     // chunk requested by the shape (before LDS limits)
+  DedispShape req;           // shape requested (before LDS limits, or the byte-quad default that did not fit)
   int64_t lds_bytes = 0;     // dynamic LDS per block
   int32_t row_dwords = 0;    // LDS dwords per staged copy of the widest channel
   DevBuf passes;             // int32 pairs (first channel, dwords per staged copy) per staging pass + end
@@ -61,6 +63,13 @@ struct RowTables {
   DevBuf dmin;               // int32 [n_tiles][nchan]: aligned first delay per DM tile
   DevBuf delays_dev;         // int32 [n_dm][nchan] (cutouts)
   std::vector<int32_t> delays_host;  // int32 [n_dm][nchan]
+  // byte-quad tile (shape.kind 1; addr then holds [nchan / 4][n_dm_pad])
+  DevBuf q_tile_pass;        // int32 [n_tiles + 1]: first pass record of each DM tile
+  DevBuf q_passes;           // int4 per pass {first quad, first copy, chunks per copy, magic} + a sentinel per tile
+  DevBuf q_copies;           // int4 per staged copy: source byte offset of each of its 4 channels
+  int64_t q_pitch = 0;       // staged pitch the quad tile needs
+  int32_t q_rec_dw = 0;      // LDS dwords of one buffer of copy records (data_dw: of copies)
+  double q_staged_dw = 0;    // LDS dwords staged per time tile, summed over DM tiles (profile)
 };
 
 // One timed kernel launch (profiling enabled).
@@ -176,7 +185,8 @@ void compute_delays(const gsp_dmt_desc *desc, const double *freqs, int32_t s, in
 std::string plan_key(const gsp_dmt_desc *desc, const double *freqs);
 
 // Dedispersion (dedisp.hip)
-DedispShape default_shape(int32_t D);
+// default: the byte-quad tile where it applies (D = 1, nchan % 4 == 0), else the 16-bit tile
+DedispShape default_shape(int32_t D, int32_t nchan);
 bool shape_supported(const DedispShape &s);
 std::string row_signature(const gsp_dmt_desc *desc, int32_t s);
 DedispShape shape_for_row(gsp_ctx *ctx, const gsp_dmt_desc *desc, int32_t s);
@@ -199,6 +209,23 @@ void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const 
                int64_t pitch_override = 0);
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 int64_t staged_pitch(const RowTables &rt);
+// Byte-quad tile (dedisp_quad.hip): tables from rt.delays_host for rt.shape
+// (kind 1); GSP_EINVAL when the row does not suit it (D > 1, nchan % 4, a
+// quad's copies wider than the LDS or the staging registers)
+bool quad_shape_supported(const DedispShape &s);
+struct QuadHost {                  // the byte-quad tile's tables on the host
+  std::vector<int32_t> tile_pass;  // first pass record of each DM tile (+ end)
+  std::vector<int32_t> passes;     // 4 ints per record: first quad, first copy, chunks per copy, division magic
+  std::vector<int32_t> copies;     // 4 ints per copy: source byte offset of each channel from the pass's first row
+  std::vector<uint32_t> addr;      // [nchan / 4][n_dm_pad] LDS dword offsets
+  int64_t pitch = 0, lds_dw = 0;   // staged pitch needed, LDS dwords of the largest pass's copies
+  int rec_max = 0;                 // most copies in a pass
+  double staged = 0;               // LDS dwords staged per time tile, all DM tiles
+  int max_q = 0;
+};
+void quad_tables_host(const RowTables &rt, QuadHost &H);
+void build_quad_tables(gsp_ctx *ctx, RowTables &rt);
+void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 
 // Search (search.hip)
 SearchTiling search_tiling(int32_t max_width);

@@ -16,18 +16,22 @@ using namespace gsp;
 
 namespace {
 
-DedispShape mk(int groups, int tpw, int waves, int chunk) {
+DedispShape mk(int groups, int tpw, int waves, int chunk, int kind = 0) {
   DedispShape d;
   d.groups = groups;
   d.tpw = tpw;
   d.waves = waves;
   d.chunk = chunk;
+  d.kind = kind;
   return d;
 }
 
+// 16-bit tile shapes, then byte-quad tile shapes (D = 1 rows with whole
+// channel quads; the others reject them)
 const DedispShape kCandidates[] = {
     mk(4, 4, 8, 16), mk(4, 4, 8, 32), mk(4, 8, 4, 16), mk(4, 8, 4, 32), mk(2, 8, 8, 16),
     mk(2, 8, 4, 32), mk(4, 4, 4, 16), mk(8, 4, 8, 16),
+    mk(4, 8, 8, 64, 1), mk(8, 4, 16, 64, 1), mk(4, 8, 16, 64, 1), mk(8, 4, 8, 64, 1), mk(4, 8, 4, 64, 1),
 };
 
 DedispShape from_abi(const gsp_shape &s) {
@@ -36,6 +40,7 @@ DedispShape from_abi(const gsp_shape &s) {
   d.tpw = s.tpw;
   d.waves = s.waves;
   d.chunk = s.chunk;
+  d.kind = s.kind;
   return d;
 }
 
@@ -53,6 +58,7 @@ int gsp_row_shape(gsp_ctx *ctx, const double *freqs, const gsp_dmt_desc *desc, i
     out->tpw = rt.shape.tpw;
     out->waves = rt.shape.waves;
     out->chunk = rt.shape.chunk;
+    out->kind = rt.shape.kind;
   });
 }
 
@@ -97,7 +103,7 @@ int gsp_autotune(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const gsp
       for (int32_t s = 0; s < desc->n_seg; ++s) {
         const std::string sig = row_signature(desc, s);
         float best_ms = 1e30f;
-        DedispShape best = default_shape(desc->seg[s].downsamp);
+        DedispShape best = default_shape(desc->seg[s].downsamp, desc->nchan);
         for (const DedispShape &cand : kCandidates) {
           ctx->tuned[sig] = cand;
           RowTables *rt = nullptr;
@@ -141,7 +147,7 @@ int gsp_tuning_save(const gsp_ctx *ctx, const char *path) {
   if (!f) return GSP_EINVAL;
   for (const auto &kv : ctx->tuned)
     f << kv.first << ' ' << kv.second.groups << ' ' << kv.second.tpw << ' ' << kv.second.waves << ' '
-      << kv.second.chunk << '\n';
+      << kv.second.chunk << ' ' << kv.second.kind << '\n';
   return f.good() ? GSP_OK : GSP_EINVAL;
 }
 
@@ -155,6 +161,7 @@ int gsp_tuning_load(gsp_ctx *ctx, const char *path) {
     std::string sig;
     DedispShape d;
     if (!(is >> sig >> d.groups >> d.tpw >> d.waves >> d.chunk)) continue;
+    if (!(is >> d.kind)) d.kind = 0;
     if (shape_supported(d)) ctx->tuned[sig] = d;
   }
   return GSP_OK;

@@ -95,7 +95,8 @@ _L.gsp_single_pulse_search.restype = C.c_int
 _L.gsp_single_pulse_search.argtypes = [P, P, C.POINTER(DmtDesc), P, C.c_int32, C.c_float, P, C.c_int64,
                                        C.POINTER(C.c_int64), P]
 class Shape(C.Structure):
-    _fields_ = [("groups", C.c_int32), ("tpw", C.c_int32), ("waves", C.c_int32), ("chunk", C.c_int32)]
+    _fields_ = [("groups", C.c_int32), ("tpw", C.c_int32), ("waves", C.c_int32), ("chunk", C.c_int32),
+                ("kind", C.c_int32)]
 
 
 _L.gsp_autotune.restype = C.c_int
@@ -334,11 +335,12 @@ class Context:
         f = _f64(freqs)
         sh = Shape()
         _check(_L.gsp_row_shape(self.h, f.ctypes.data, C.byref(desc), int(seg), C.byref(sh)), self.h)
-        return (sh.groups, sh.tpw, sh.waves, sh.chunk)
+        return (sh.groups, sh.tpw, sh.waves, sh.chunk, sh.kind)
 
-    def set_row_shape(self, freqs, desc: DmtDesc, seg: int, groups: int, tpw: int, waves: int, chunk: int):
+    def set_row_shape(self, freqs, desc: DmtDesc, seg: int, groups: int, tpw: int, waves: int, chunk: int,
+                      kind: int = 0):
         f = _f64(freqs)
-        sh = Shape(int(groups), int(tpw), int(waves), int(chunk))
+        sh = Shape(int(groups), int(tpw), int(waves), int(chunk), int(kind))
         _check(_L.gsp_set_row_shape(self.h, f.ctypes.data, C.byref(desc), int(seg), C.byref(sh)), self.h)
 
     def tuning_save(self, path: str):

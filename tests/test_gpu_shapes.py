@@ -1,5 +1,6 @@
 """Every dedispersion launch shape the autotuner may pick gives bit-exact
-results (ragged channels, trials and samples; uint8 and uint16 staging)."""
+results (ragged channels, trials and samples; uint8 and uint16 staging; the
+16-bit tile and the byte-quad tile)."""
 import numpy as np
 import pytest
 
@@ -11,6 +12,10 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 8, 16), (4, 4, 8, 32), (4, 8, 4, 16), (4, 8, 4, 32), (2, 8, 8, 16), (2, 8, 4, 32),
           (4, 4, 4, 16), (8, 4, 8, 16), (4, 4, 1, 3), (2, 8, 1, 1)]
+# byte-quad tile (groups, tpw, waves, quads per pass, kind 1): the autotuner's
+# candidates, one-quad and three-quad passes, a single wave
+QUAD_SHAPES = [(8, 4, 8, 64, 1), (8, 4, 16, 64, 1), (8, 2, 16, 64, 1), (8, 2, 8, 64, 1), (4, 8, 8, 64, 1),
+               (16, 2, 16, 64, 1), (4, 4, 8, 64, 1), (8, 4, 16, 3, 1), (8, 4, 8, 1, 1), (8, 2, 1, 64, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -48,3 +53,56 @@ def test_autotune_then_parity(case):
     views = gsp.segment_views(desc, dmt)
     for s in range(desc.n_seg):
         assert (views[s].cpu().numpy() == ref[s]).all()
+
+
+@pytest.fixture(scope="module")
+def quad_case(dev):
+    """A multiple of 4 channels, ragged trials and samples, a D = 1 row (the
+    byte-quad tile's) and a D = 2 row (which keeps the 16-bit tile)."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    w = synth.small(nchan=516, nsamp=9001, segments=[(0.0, 0.3, 71, 1), (21.3, 1.0, 13, 2)], tsamp=98.304e-6,
+                    n_pulses=2)
+    X = w.generate()
+    ref = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    fb = torch.from_numpy(X).to("cuda")
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    ctx = gsp.Context(0)
+    yield gsp, ctx, w, fb, desc, ref, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_quad_is_default_for_d1(quad_case):
+    gsp, ctx, w, fb, desc, ref, torch = quad_case
+    assert ctx.row_shape(w.freqs, desc, 0)[4] == 1
+    assert ctx.row_shape(w.freqs, desc, 1)[4] == 0
+    with pytest.raises(gsp.GspError):  # D = 2 rows are summed as 16-bit samples
+        ctx.set_row_shape(w.freqs, desc, 1, 8, 4, 8, 64, 1)
+
+
+@pytest.mark.parametrize("shape", QUAD_SHAPES)
+def test_quad_shape_bit_exact(quad_case, shape):
+    gsp, ctx, w, fb, desc, ref, torch = quad_case
+    say(f"[case] quad shape {shape}")
+    ctx.set_row_shape(w.freqs, desc, 0, *shape)
+    used = ctx.row_shape(w.freqs, desc, 0)
+    assert used[4] == 1 and used[3] <= shape[3], used
+    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    views = gsp.segment_views(desc, dmt)
+    for s in range(desc.n_seg):
+        assert (views[s].cpu().numpy() == ref[s]).all(), (shape, s)
+
+
+def test_quad_shape_rejected_when_copies_do_not_fit(quad_case):
+    """1024 outputs per wave and a single wave: a quad's copies exceed what
+    one wave's staging registers hold, so the shape is refused with an error
+    and the row keeps its previous tables."""
+    gsp, ctx, w, fb, desc, ref, torch = quad_case
+    ctx.set_row_shape(w.freqs, desc, 0, 8, 4, 8, 64, 1)
+    with pytest.raises(gsp.GspError):
+        ctx.set_row_shape(w.freqs, desc, 0, 16, 2, 1, 64, 1)
+    assert ctx.row_shape(w.freqs, desc, 0)[:3] == (8, 4, 8)
+    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    views = gsp.segment_views(desc, dmt)
+    assert (views[0].cpu().numpy() == ref[0]).all()
