@@ -28,11 +28,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DM-trial×samples/s & real-time factor (4096 ch); batched+CNN vs plain"
 PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 VALU ops/s
-# The dedispersion kernel adds two 16-bit sample sums per 32-bit add, so the
-# ceiling of its instruction mix, in sample additions, is twice the int32 rate.
-PEAK_SAMPLE_ADDS = 2 * PEAK_INT32_OPS
-# LDS read rates measured on the MI355X for the kernel's access pattern, B/clk/CU
-LDS_READ2ST64 = 110.2  # ds_read2st64_b32, offsets from registers (the kernel's form)
+# Sample additions per 32-bit VALU lane operation: the 16-bit tile adds two
+# 16-bit sample sums per packed add; the byte-quad tile adds four bytes per
+# v_sad_u8.  Their ALU ceilings in sample additions:
+PEAK_SAMPLE_ADDS = {"dedisperse": 2 * PEAK_INT32_OPS, "dedisperse_quad": 4 * PEAK_INT32_OPS}
+# LDS bytes the kernels read per sample addition (a dword holds two 16-bit
+# samples, or four channels' bytes)
+LDS_BYTES_PER_ADD = {"dedisperse": 2.0, "dedisperse_quad": 1.0}
+KERNEL_NAME = {"dedisperse": "k_dedisp", "dedisperse_quad": "k_dedisp_quad"}
+# LDS read rates measured on the MI355X for the kernels' access pattern, B/clk/CU
+LDS_READ2ST64 = 110.2  # ds_read2st64_b32, offsets from registers (the kernels' form)
 LDS_B128 = 176.7       # ds_read_b128 at 16-byte aligned addresses
 
 
@@ -57,8 +62,8 @@ def describe(w, desc):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_realistic_traffic.md")
-DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_tile.h")]  # the kernel's device code
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_quad_realistic_traffic.md")
+DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_quad.hip")]  # the kernel's device code
 
 
 def kernel_source_hash() -> str:
@@ -71,9 +76,10 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(workload_name: str):
-    """HBM bytes per dedispersion launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel), or None
-    when there is none for this workload or the kernel source changed since."""
+    """HBM bytes per launch of the byte-quad dedispersion kernel (the D = 1
+    row) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy kernel), or None when there is none for
+    this workload or the kernel source changed since."""
     if workload_name != "realistic" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -328,7 +334,7 @@ def shape_sweep(w):
                 ctx.dedisperse(fb, w.freqs, d1, out=out)
             p = ctx.profile_read()
             ctx.profile_enable(False)
-            ms = p["dedisperse"][1] / 2
+            ms = sum(p[k][1] for k in ("dedisperse", "dedisperse_quad") if k in p) / 2
             used = tuple(ctx.row_shape(w.freqs, d1, 0))
             print(f"| {s} | {seg[3]} | {seg[2]} | {c} | {used} | {ms:.2f} | {adds / ms / 1e9:.2f} |", flush=True)
         del out
@@ -474,33 +480,46 @@ def main():
     cfg["autotuned"] = shapes is not None
     value = cfg["dm_trial_samples"] / (ms / 1e3)
     rtf = (w.nsamp * w.tsamp) / (ms / 1e3)
-    n, tot_ms, adds = prof["dedisperse"]
+    # the dominant kernel: the dedispersion tile with the most time per step
+    dom = max((k for k in PEAK_SAMPLE_ADDS if k in prof), key=lambda k: prof[k][1])
+    n, tot_ms, adds = prof[dom]
     achieved = adds / (tot_ms / 1e3)
+    peak = PEAK_SAMPLE_ADDS[dom]
+    lds_b = LDS_BYTES_PER_ADD[dom]
     kernels = {k: {"launches_per_step": v[0] / args.steps, "ms_per_step": v[1] / args.steps,
                    "avg_launch_ms": v[1] / v[0],
-                   ("adds_per_s" if k == "dedisperse" else "bytes_per_s"): v[2] / (v[1] / 1e3)}
+                   ("adds_per_s" if k.startswith("dedisperse") else "bytes_per_s"): v[2] / (v[1] / 1e3)}
                for k, v in prof.items()}
+    all_adds = sum(prof[k][2] for k in PEAK_SAMPLE_ADDS if k in prof)
+    all_ms = sum(prof[k][1] for k in PEAK_SAMPLE_ADDS if k in prof)
     out = {
         "metric": METRIC, "value": value, "unit": "DM-trial×samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8->int32", "data": "synthetic", "config": cfg,
         "rtf": rtf,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SAMPLE_ADDS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_SAMPLE_ADDS, "traffic": measured_traffic(w.name),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TOP/s",
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(w.name) if dom == "dedisperse_quad" else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": "k_dedisp", "work": "integer adds (n_dm * n_out * nchan per launch)",
-                     "peak_note": "two 16-bit sample additions per packed 32-bit VALU add: 2 x 256 CUs x 64 lanes "
-                                  "x 2.4 GHz; the kernel is bound by its LDS reads (see 'lds'), at about 34 T "
-                                  "adds/s with its read form"},
-        "lds": {"what": "LDS read bandwidth of the dedispersion kernel: 2 bytes of staged samples per sample add "
-                        "(one ds_read2st64_b32 of 512 bytes per 256 adds and wave)",
-                "achieved_TBps": 2.0 * achieved / 1e12,
+                     "kernel": KERNEL_NAME[dom], "launches_per_step": n / args.steps,
+                     "work": "integer sample additions (n_dm * n_out * nchan per launch)",
+                     "peak_note": ("four 8-bit sample additions per v_sad_u8 lane operation: 4 x 256 CUs x 64 "
+                                   "lanes x 2.4 GHz" if dom == "dedisperse_quad" else
+                                   "two 16-bit sample additions per packed 32-bit VALU add: 2 x 256 CUs x 64 "
+                                   "lanes x 2.4 GHz") +
+                                  "; the kernel is bound by its LDS reads (see 'lds') and the VALU work of "
+                                  "staging them",
+                     "all_dedispersion": {"adds_per_s": all_adds / (all_ms / 1e3), "ms_per_step": all_ms / args.steps,
+                                          "what": "every dedispersion launch of the step (both tiles)"}},
+        "lds": {"what": f"LDS read bandwidth of {KERNEL_NAME[dom]}: {lds_b:g} byte(s) of staged samples per "
+                        "sample addition, read as ds_read2st64_b32",
+                "achieved_TBps": lds_b * achieved / 1e12,
                 "peak_form_TBps": LDS_READ2ST64 * 256 * 2.4e9 / 1e12,
-                "frac_form": 2.0 * achieved / (LDS_READ2ST64 * 256 * 2.4e9),
+                "frac_form": lds_b * achieved / (LDS_READ2ST64 * 256 * 2.4e9),
                 "peak_b128_TBps": LDS_B128 * 256 * 2.4e9 / 1e12,
-                "frac_b128": 2.0 * achieved / (LDS_B128 * 256 * 2.4e9),
-                "note": "measured on MI355X with this access pattern and the packed adds: ds_read2st64_b32 with "
-                        "register offsets 110.2 B/clk/CU, ds_read_b128 (16-byte aligned) 176.7 B/clk/CU"},
+                "frac_b128": lds_b * achieved / (LDS_B128 * 256 * 2.4e9),
+                "note": "measured on MI355X: ds_read2st64_b32 with register offsets 110.2 B/clk/CU, "
+                        "ds_read_b128 (16-byte aligned) 176.7 B/clk/CU"},
         "kernels": kernels,
         "candidates": int(len(c)), "events": int(ng),
         "triage": None if net is None else {

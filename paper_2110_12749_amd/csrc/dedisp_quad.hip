@@ -26,8 +26,8 @@
 // the LDS; the per-(quad, trial) LDS offsets are precomputed as for
 // k_dedisp.  A pass's copies are built in registers from the channel-major
 // uint8 rows k_stage writes, 16 bytes (4 outputs of 4 channels) per thread
-// at a time: 8 aligned bytes per channel, v_alignbyte, a 4x4 byte transpose
-// by v_perm.  Consecutive threads write consecutive 16-byte chunks, so the
+// at a time: one dword load per channel from its (unaligned) start, then a
+// 4x4 byte transpose by v_perm.  Consecutive threads write consecutive 16-byte chunks, so the
 // staging writes are free of LDS bank conflicts.
 #include <algorithm>
 #include <cstring>
@@ -40,7 +40,8 @@ namespace gsp {
 struct QuadArgs {
   const uint8_t *Y;          // channel-major staged rows [nchan][pitch]
   int64_t pitch;
-  const uint32_t *addr;      // [nq][n_dm_pad] LDS dword offset per (quad, trial) within its pass
+  const uint32_t *addr;      // [nq][n_dm_pad / 2] LDS dword offsets per (quad, trial) in their pass's
+                             // buffer, two trials (2m, 2m + 1) per dword in its low and high halves
   const int32_t *tile_pass;  // [n_dm_tiles + 1] first pass record of each DM tile
   const int4 *passes;        // {first quad, first copy, chunks per copy, division magic}; a sentinel ends each tile
   const int4 *copies;        // per copy and channel: source byte offset from the pass's first row, at output 0
@@ -51,8 +52,12 @@ struct QuadArgs {
   int32_t rec_dw;            // LDS dwords of one buffer of copy records (a multiple of 4)
 };
 
-// Staging chunks per thread and pass (registers: 9 per chunk)
-__host__ __device__ constexpr int quad_chunks(int K, int TPW) { return K * TPW >= 32 ? (K >= 16 ? 3 : 4) : 6; }
+// Staging chunks per thread and pass (registers: 4 per chunk)
+__host__ __device__ constexpr int quad_chunks(int K, int TPW) { return K * TPW >= 32 ? 5 : 8; }
+
+// A dword load from any byte address (the code object assumes unaligned
+// global access, as HSA configures it)
+typedef uint32_t u32_unaligned __attribute__((aligned(1)));
 
 // Staging: a pass's copies are split into 16-byte chunks (4 output samples
 // of the quad's 4 channels); consecutive threads build consecutive chunks,
@@ -94,9 +99,8 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
   fetch_window(0);
 
   int4 nrec = make_int4(0, 0, 0, 0);  // this thread's copy record of a coming pass
-  uint32_t pw[CM][4][2];              // per chunk and channel: the 8 aligned bytes holding its 4 samples
-  uint32_t psh[CM];                   // per chunk: byte shift of each channel (bits 8 ch .. 8 ch + 1)
-  uint32_t roff[TPW], noff[TPW];
+  uint32_t pw[CM][4];                 // per chunk and channel: its 4 samples
+  uint32_t roff[TPW / 2], noff[TPW / 2];  // lane l: the wave's trial offsets at quad l of the pass, in pairs
   auto load_rec = [&](int j) {
     const int nc = c_begin(j + 1) - c_begin(j);
     nrec = a.copies[c_begin(j) + min(tid, nc - 1)];
@@ -119,45 +123,45 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
       const int4 r = rec_lds[k];
       const int rv[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(base + (uint32_t)((rv[ch] + tc) & ~3));
-        pw[i][ch][0] = src[0];
-        pw[i][ch][1] = src[1];
-      }
-      // the byte shift of channel ch is its record's offset mod 4 (tc is a
-      // multiple of 4): the records' low bytes, packed one per channel
-      psh[i] = __builtin_amdgcn_perm((uint32_t)r.y, (uint32_t)r.x, 0x0c0c0400u) |
-               __builtin_amdgcn_perm((uint32_t)r.w, (uint32_t)r.z, 0x04000c0cu);
+      for (int ch = 0; ch < 4; ++ch) pw[i][ch] = *reinterpret_cast<const u32_unaligned *>(base + (uint32_t)(rv[ch] + tc));
     }
-    const uint32_t *o = a.addr + (int64_t)(qb + min(lane, qe - qb - 1)) * a.n_dm_pad + i_wave;
-#pragma unroll
-    for (int t = 0; t < TPW; t += 2) {
-      const uint2 v = *reinterpret_cast<const uint2 *>(o + t);
-      noff[t] = v.x;
-      noff[t + 1] = v.y;
+    const uint32_t *o = a.addr + (int64_t)(qb + min(lane, qe - qb - 1)) * (a.n_dm_pad >> 1) + (i_wave >> 1);
+    if constexpr (TPW == 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(o);
+      noff[0] = v.x;
+      noff[1] = v.y;
+      noff[2] = v.z;
+      noff[3] = v.w;
+    } else if constexpr (TPW == 4) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(o);
+      noff[0] = v.x;
+      noff[1] = v.y;
+    } else {
+      noff[0] = o[0];
     }
   };
-  auto store = [&](int j) {  // registers -> LDS: chunk g of the pass at dwords [4g, 4g + 4) of its buffer
+  // registers -> LDS: chunk i of this thread (pass chunk g = tid + i *
+  // nthreads) at dwords [4g, 4g + 4) of the pass's buffer; the chunks of a
+  // wave's store cover consecutive 16-byte slots (no bank conflicts)
+  auto store_chunk = [&](int j, int i) {
     const int nchk = (c_begin(j + 1) - c_begin(j)) * chunks_of(j);
-    uint4 *dst4 = reinterpret_cast<uint4 *>(data_buf(j));
-#pragma unroll
-    for (int i = 0; i < CM; ++i) {
-      const int g = tid + i * nthreads;
-      if (g < nchk) {
-        uint32_t w[4];  // w[ch]: the chunk's 4 samples of channel ch
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) w[ch] = __builtin_amdgcn_alignbyte(pw[i][ch][1], pw[i][ch][0], psh[i] >> (8 * ch));
-        // 4x4 byte transpose: x01 interleaves channels 0 and 1, x23 channels 2 and 3
-        // (selector byte k < 4: byte k of the second operand, 4..7: byte k-4 of the first)
-        const uint32_t x01l = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);
-        const uint32_t x01h = __builtin_amdgcn_perm(w[1], w[0], 0x07030602u);
-        const uint32_t x23l = __builtin_amdgcn_perm(w[3], w[2], 0x05010400u);
-        const uint32_t x23h = __builtin_amdgcn_perm(w[3], w[2], 0x07030602u);
-        dst4[g] = make_uint4(
-            __builtin_amdgcn_perm(x23l, x01l, 0x05040100u), __builtin_amdgcn_perm(x23l, x01l, 0x07060302u),
-            __builtin_amdgcn_perm(x23h, x01h, 0x05040100u), __builtin_amdgcn_perm(x23h, x01h, 0x07060302u));
-      }
+    const int g = tid + i * nthreads;
+    if (g < nchk) {
+      const uint32_t *w = pw[i];  // w[ch]: the chunk's 4 samples of channel ch
+      // 4x4 byte transpose: x01 interleaves channels 0 and 1, x23 channels 2 and 3
+      // (selector byte k < 4: byte k of the second operand, 4..7: byte k-4 of the first)
+      const uint32_t x01l = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);
+      const uint32_t x01h = __builtin_amdgcn_perm(w[1], w[0], 0x07030602u);
+      const uint32_t x23l = __builtin_amdgcn_perm(w[3], w[2], 0x05010400u);
+      const uint32_t x23h = __builtin_amdgcn_perm(w[3], w[2], 0x07030602u);
+      reinterpret_cast<uint4 *>(data_buf(j))[g] = make_uint4(
+          __builtin_amdgcn_perm(x23l, x01l, 0x05040100u), __builtin_amdgcn_perm(x23l, x01l, 0x07060302u),
+          __builtin_amdgcn_perm(x23h, x01h, 0x05040100u), __builtin_amdgcn_perm(x23h, x01h, 0x07060302u));
     }
+  };
+  auto store = [&](int j) {
+#pragma unroll
+    for (int i = 0; i < CM; ++i) store_chunk(j, i);
   };
 
   uint32_t acc[TPW][K];
@@ -168,7 +172,9 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
 
   const uint32_t *cur = lds;  // buffer of the pass being summed
   auto ld = [&](int q, int t, uint32_t *v) {  // trial t's dwords of quad q (q uniform)
-    const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)roff[t], q);
+    // one readlane per two trials; the halves are split on the scalar unit
+    const uint32_t pair = (uint32_t)__builtin_amdgcn_readlane((int)roff[t >> 1], q);
+    const uint32_t o = (t & 1) ? pair >> 16 : pair & 0xFFFFu;
     const uint32_t *src = cur + o + lane;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = src[64 * k];
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
   for (int kc = 0; kc < n_pass; ++kc) {
     if (kc + 3 > w0 + 63) fetch_window(kc);  // records kc .. kc + 3 are read below
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) roff[t] = noff[t];
+    for (int t = 0; t < TPW / 2; ++t) roff[t] = noff[t];
     if (kc + 1 < n_pass) load_data(kc + 1);  // samples of the next pass in flight
     if (kc + 2 < n_pass) load_rec(kc + 2);
 
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
 static constexpr int64_t kQuadLdsBudget = 80 * 1024;  // two workgroups per CU
 static constexpr int64_t kQuadLdsMax = 160 * 1024;
 static constexpr int kQuadPassMax = 64;               // quads per pass: one per lane for the offsets
-static constexpr int kQuadRecMax = 256;               // copies per pass (their records share the LDS)
+static constexpr int kQuadRecMax = 128;               // copies per pass (their records share the LDS)
 
 bool quad_shape_supported(const DedispShape &s) {
   const int kt = s.groups * 16 + s.tpw;
@@ -279,7 +285,7 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   H.tile_pass.clear();
   H.passes.clear();
   H.copies.clear();
-  H.addr.assign((size_t)nq * n_dm_pad, 0);
+  H.addr.assign((size_t)nq * (n_dm_pad / 2), 0);
   std::vector<int32_t> cp_start;  // per copy: start sample of each channel (offsets need the final pitch)
   std::vector<int32_t> cp_q, cp_qb;
   int64_t max_dw = 0, max_cu = 0;
@@ -356,7 +362,9 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
         for (int j = 0; j < MT; ++j) {
           const Pat &p = P[pat_of[qq][j]];
           const int32_t o0 = delay(i0 + j, 4 * qq);
-          H.addr[(size_t)qq * n_dm_pad + i0 + j] = (uint32_t)((int64_t)(slot + pat_of[qq][j]) * CU * 4 + (o0 - p.lo));
+          const int64_t off = (int64_t)(slot + pat_of[qq][j]) * CU * 4 + (o0 - p.lo);
+          if (off >= 65536) fail(GSP_EINVAL, "byte-quad LDS offset beyond 16 bits");
+          H.addr[(size_t)qq * (n_dm_pad / 2) + (i0 + j) / 2] |= (uint32_t)off << (16 * ((i0 + j) & 1));
         }
         slot += (int32_t)P.size();
       }
@@ -374,8 +382,8 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   H.tile_pass.push_back((int32_t)(H.passes.size() / 4));
   if (cp_q.size() >= (size_t)INT32_MAX / 4) fail(GSP_EOVERFLOW, "byte-quad tables too large");
 
-  // staged pitch: a chunk reads 8 bytes from sample t0 + s + 4 c (aligned
-  // down to 4) with s <= max_delay and c below the pass's chunk count
+  // staged pitch: a chunk reads 4 bytes from sample t0 + s + 4 c with
+  // s <= max_delay and c below the pass's chunk count
   const int64_t far = (n_t - 1) * T + rt.max_delay + 4 * max_cu + 8;
   H.pitch = (std::max(far, rt.N) + 255) / 256 * 256;
   if (H.pitch > pitch_ub) fail(GSP_EINVAL, "byte-quad pitch bound");
@@ -442,7 +450,7 @@ void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hip
   const int64_t n_t = (rt.n_out + T - 1) / T;
   if ((int64_t)a.n_dm_tiles * n_t >= (1LL << 31)) fail(GSP_EOVERFLOW, "too many dedispersion tiles");
   a.n_t_tiles = (int32_t)n_t;
-  ProfScope prof(ctx, "dedisperse", st, (double)rt.n_dm * (double)rt.n_out * (double)rt.nchan);
+  ProfScope prof(ctx, "dedisperse_quad", st, (double)rt.n_dm * (double)rt.n_out * (double)rt.nchan);
   switch (sh.groups * 16 + sh.tpw) {
     case 8 * 16 + 4: launch_q<8, 4>(a, sh.waves, rt.lds_bytes, st); break;
     case 8 * 16 + 2: launch_q<8, 2>(a, sh.waves, rt.lds_bytes, st); break;

@@ -217,7 +217,7 @@ struct QuadHost {                  // the byte-quad tile's tables on the host
   std::vector<int32_t> tile_pass;  // first pass record of each DM tile (+ end)
   std::vector<int32_t> passes;     // 4 ints per record: first quad, first copy, chunks per copy, division magic
   std::vector<int32_t> copies;     // 4 ints per copy: source byte offset of each channel from the pass's first row
-  std::vector<uint32_t> addr;      // [nchan / 4][n_dm_pad] LDS dword offsets
+  std::vector<uint32_t> addr;      // [nchan / 4][n_dm_pad / 2] LDS dword offsets, two trials per dword
   int64_t pitch = 0, lds_dw = 0;   // staged pitch needed, LDS dwords of the largest pass's copies
   int rec_max = 0;                 // most copies in a pass
   double staged = 0;               // LDS dwords staged per time tile, all DM tiles
