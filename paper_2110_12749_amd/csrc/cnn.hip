@@ -401,6 +401,8 @@ struct CutoutArgs {
   CutRow row[GSP_MAX_SEG];
   uint16_t *out;  // bf16 [n][2][64][64]
   uint32_t *ftsums;  // [n][64 bands][64 bins]: frequency-time band sums (k_cutout_ft writes, k_cutout reads)
+  const uint8_t *ycm;  // channel-major copy of fb, rows of cm_pitch bytes (k_cutout_ft_cm)
+  int64_t cm_pitch;
 };
 
 // Sum of a uint32 over the 64 lanes of a wave (DPP shifts inside rows of 16,
@@ -560,6 +562,9 @@ __device__ void cutout_images(int64_t e, int width, int dm_index, int n_dm, int 
 
 // Raw rows of one band staged per wave for the tiled band sums.
 static constexpr int kTileRows = 320;
+// batches of at least this many candidates read a channel-major copy of the
+// input (k_cutout_ft_cm); smaller ones read the recorded rows (k_cutout_ft)
+static constexpr int64_t kCutStageMin = 256;
 
 __device__ __forceinline__ int wave_min_i32(int v) {
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -710,6 +715,53 @@ __global__ __launch_bounds__(256) void k_cutout_ft(CutoutArgs a) {
       }
     }
     a.ftsums[(k * 64 + band) * 64 + lane] = mine;
+  }
+}
+
+// The same band sums from a channel-major copy of the filterbank, for large
+// batches (the copy is one transpose of the whole input): one wave per
+// (event, band), lane b sums bin b over the band's channels.  For a channel
+// the bins of the lanes are consecutive byte runs of its row (r D bytes
+// each), read as unaligned dwords and summed by v_sad_u8, so a wave's loads
+// are contiguous whatever the delays; no cross-lane reduction.
+__device__ __forceinline__ uint32_t load_u32_any(const uint8_t *p) {
+  typedef uint32_t u32_unaligned __attribute__((aligned(1)));
+  return *reinterpret_cast<const u32_unaligned *>(p);
+}
+__global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = blockIdx.x & 7;
+  const int64_t per_xcd = gridDim.x >> 3;
+  for (int64_t j = blockIdx.x >> 3;; j += per_xcd) {
+    const int64_t k = (j >> 4) * 8 + x;
+    if (k >= a.n) break;
+    const int band = (int)(j & 15) * 4 + wave;
+    const gsp_candidate c = a.cand[k];
+    const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
+                    c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
+                    c.t_peak + c.width - 1 < a.row[c.seg].n_out;
+    if (!ok) continue;  // k_cutout writes zero images and reads nothing here
+    const CutRow R = a.row[c.seg];
+    const int nchan = a.nchan, D = R.D;
+    const int32_t *dly = R.delays + (int64_t)c.dm_index * nchan;
+    const int64_t e = c.t_peak + c.width - 1;
+    const int r = max(1, min(a.rmax, c.width / 8));
+    const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
+    // bin `lane`: downsampled samples [tb, tb + r) of each channel after its
+    // delay, those before the start left out (k_cutout scales the bin)
+    const int64_t tb = e - (int64_t)(64 - lane) * r + 1;
+    const int64_t tlo = max(tb, (int64_t)0);
+    const int nb = (int)max((int64_t)0, tb + r - tlo) * D;  // raw bytes of the bin
+    uint32_t s = 0;
+    for (int ch = cb; ch < ce; ++ch) {
+      const uint8_t *p = a.ycm + (int64_t)ch * a.cm_pitch + (tlo + dly[ch]) * D;
+      for (int u = 0; u < nb; u += 4) {
+        uint32_t w = load_u32_any(p + u);
+        if (u + 4 > nb) w &= 0xFFFFFFFFu >> (8 * (u + 4 - nb));
+        s = __builtin_amdgcn_sad_u8(w, 0u, s);
+      }
+    }
+    a.ftsums[(k * 64 + band) * 64 + lane] = s;
   }
 }
 
@@ -1300,9 +1352,19 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     ctx->ftsums.device = ctx->device;
     ctx->ftsums.reserve((size_t)n * 64 * 64 * sizeof(uint32_t));
     a.ftsums = ctx->ftsums.as<uint32_t>();
-    // a multiple of 8 workgroups (the kernel's XCD mapping needs it)
-    hipLaunchKernelGGL(k_cutout_ft, dim3((unsigned)std::min<int64_t>((n + 7) / 8 * 8 * 16, 256 * 64)), dim3(256), 0,
-                       st, a);
+    // a multiple of 8 workgroups (the kernels' XCD mapping needs it)
+    const dim3 ft_grid((unsigned)std::min<int64_t>((n + 7) / 8 * 8 * 16, 256 * 64));
+    if (n >= kCutStageMin) {
+      // a large batch: one channel-major copy of the input (in the staging
+      // buffer, which every dedispersion call restages), then contiguous reads
+      const int64_t pitch = (desc->nsamp + 4 + 255) / 256 * 256;
+      stage_raw(ctx, fb, desc->nsamp, desc->nchan, pitch, st);
+      a.ycm = ctx->staged.as<uint8_t>();
+      a.cm_pitch = pitch;
+      hipLaunchKernelGGL(k_cutout_ft_cm, ft_grid, dim3(256), 0, st, a);
+    } else {
+      hipLaunchKernelGGL(k_cutout_ft, ft_grid, dim3(256), 0, st, a);
+    }
     const unsigned grid = (unsigned)std::min<int64_t>(n, 256 * 8);
     hipLaunchKernelGGL(k_cutout, dim3(grid), dim3(256), 0, st, a);
     check_hip(hipGetLastError(), "launch cutouts");

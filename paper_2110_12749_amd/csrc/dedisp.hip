@@ -377,6 +377,19 @@ void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const 
   check_hip(hipGetLastError(), "launch staging kernel");
 }
 
+void stage_raw(gsp_ctx *ctx, const uint8_t *fb, int64_t nsamp, int32_t nchan, int64_t pitch, hipStream_t st) {
+  if (pitch < nsamp || pitch % 256) fail(GSP_EINVAL, "staging pitch");
+  ctx->staged.device = ctx->device;
+  ctx->staged.reserve((size_t)pitch * nchan + 256);
+  dim3 grid((unsigned)((pitch + kStageT - 1) / kStageT), (unsigned)((nchan + kStageC - 1) / kStageC));
+  ProfScope prof(ctx, "stage", st, (double)nsamp * nchan + (double)pitch * nchan);
+  const uintptr_t fa = reinterpret_cast<uintptr_t>(fb);
+  const int mode = (nchan % 16 == 0 && fa % 16 == 0) ? 2 : ((nchan % 4 == 0 && fa % 4 == 0) ? 1 : 0);
+  auto k = mode == 2 ? k_stage<uint8_t, 2> : (mode == 1 ? k_stage<uint8_t, 1> : k_stage<uint8_t, 0>);
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, st, fb, nsamp, nchan, 1, nsamp, ctx->staged.as<uint8_t>(), pitch);
+  check_hip(hipGetLastError(), "launch staging kernel");
+}
+
 template <int K, int TPW>
 static void launch_k(const DedispArgs &a, int waves, int64_t lds, int D, hipStream_t st) {
   const int G = a.n_dm_tiles * a.n_t_tiles;

@@ -209,6 +209,9 @@ void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const 
                int64_t pitch_override = 0);
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 int64_t staged_pitch(const RowTables &rt);
+// Channel-major uint8 copy of the whole filterbank into ctx->staged, rows of
+// `pitch` bytes (a multiple of 256, >= nsamp; bytes past nsamp are zero)
+void stage_raw(gsp_ctx *ctx, const uint8_t *fb, int64_t nsamp, int32_t nchan, int64_t pitch, hipStream_t st);
 // Byte-quad tile (dedisp_quad.hip): tables from rt.delays_host for rt.shape
 // (kind 1); GSP_EINVAL when the row does not suit it (D > 1, nchan % 4, a
 // quad's copies wider than the LDS or the staging registers)

@@ -227,10 +227,12 @@ def test_save_load_roundtrip(env, tmp_path):
 
 # --- cutouts -------------------------------------------------------------------
 
-def cutout_case(env, w, extra):
+def cutout_case(env, w, extra, batch=0, check=None):
     """GPU cutouts of the search's candidates plus `extra` (seg, dm_index,
     t_peak, width) against the oracle, bf16 bit for bit up to rare one-step
-    rounding differences."""
+    rounding differences.  batch > 0: random valid candidates are added up to
+    that many (a batch large enough for the channel-major path) and the
+    oracle checks the candidates listed in `check` (default: all)."""
     gsp, ctx, torch = env
     X = w.generate()
     fb = torch.from_numpy(X).cuda()
@@ -242,12 +244,24 @@ def cutout_case(env, w, extra):
     for k, (s, i, t, wd) in enumerate(extra):
         more[k]["seg"], more[k]["dm_index"], more[k]["t_peak"], more[k]["width"] = s, i, t, wd
     c = np.concatenate([c, more])
+    if batch > len(c):
+        rng = np.random.default_rng(5)
+        fill = np.zeros(batch - len(c), c.dtype)
+        fill["seg"] = rng.integers(0, desc.n_seg, len(fill))
+        for k in range(len(fill)):
+            s = int(fill[k]["seg"])
+            wd = int(rng.choice(w.widths))
+            fill[k]["dm_index"] = rng.integers(0, desc.seg[s].n_dm)
+            fill[k]["width"] = wd
+            fill[k]["t_peak"] = rng.integers(0, desc.n_out[s] - wd + 1)
+        c = np.concatenate([c, fill])
     say(f"[case] cutouts {w.name}: {len(c)} candidates, widths {sorted(set(c['width'].tolist()))}")
     out = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, c).cpu().numpy().view(np.uint16)
     rows = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
     per_row = {}
     total_px, diff_px = 0, 0
-    for k, cand in enumerate(c):
+    for k in (range(len(c)) if check is None else check):
+        cand = c[k]
         s = int(cand["seg"])
         if s not in per_row:
             seg = w.segments[s]
@@ -307,6 +321,26 @@ def test_cutouts_tiled_bands_high_dm(env):
     # (row, trial, t_peak, width) inside their rows (n_out 15288 and 2378)
     extra = [(0, 5, 3000, 64), (0, 15, 100, 8), (1, 6, 2000, 64), (1, 0, 10, 16), (1, 11, 2300, 8)]
     cutout_case(env, w, extra)
+
+
+@pytest.mark.parametrize("case", ["multirow", "realistic_high_dm"])
+def test_cutouts_large_batch(env, case):
+    """A batch of 300 candidates: the band sums come from a channel-major
+    copy of the input (lane per bin, unaligned dword loads).  The oracle checks
+    the search's candidates, the edge cases and every 9th random one."""
+    if case == "multirow":
+        segs = [(0.0, 1.0, 40, 1), (40.0, 2.0, 70, 2), (180.0, 4.0, 12, 4)]
+        w = synth.small(nchan=192, nsamp=6000, segments=segs, n_pulses=3, seed_offset=60,
+                        widths=[1, 2, 4, 8, 16, 32, 64])
+        extra = [(1, 69, 10, 16), (2, 11, 0, 3), (2, 0, 200, 33), (1, 30, 1, 2), (0, 0, 0, 1), (0, 39, 5546 - 64, 64)]
+    else:
+        segs = [(600.0, 1.0, 16, 4), (1480.0, 3.0, 12, 8), (0.0, 0.5, 24, 1)]
+        w = synth.small(nchan=4096, nsamp=90000, segments=segs, tsamp=49.152e-6, n_pulses=2, seed_offset=91,
+                        widths=[1, 2, 4, 8, 16, 32, 64])
+        extra = [(0, 5, 3000, 64), (0, 15, 100, 8), (1, 6, 2000, 64), (1, 0, 10, 16), (1, 11, 2300, 8),
+                 (2, 23, 0, 64), (2, 0, 1, 1)]
+    first = 12 + len(extra)  # at most: the search's top candidates + the edge cases
+    cutout_case(env, w, extra, batch=300, check=list(range(first)) + list(range(first, 300, 9)))
 
 
 def test_cutouts_invalid_candidates_give_zero_images(env):
