@@ -36,6 +36,7 @@ PEAK_SAMPLE_ADDS = {"dedisperse": 2 * PEAK_INT32_OPS, "dedisperse_quad": 4 * PEA
 # samples, or four channels' bytes)
 LDS_BYTES_PER_ADD = {"dedisperse": 2.0, "dedisperse_quad": 1.0}
 KERNEL_NAME = {"dedisperse": "k_dedisp", "dedisperse_quad": "k_dedisp_quad"}
+QUAD_KERNEL_BY_KIND = {1: "k_dedisp_quad", 2: "k_dedisp_quad_pc"}  # the byte-quad tile's kernels by shape kind
 # LDS read rates measured on the MI355X for the kernels' access pattern, B/clk/CU
 LDS_READ2ST64 = 110.2  # ds_read2st64_b32, offsets from registers (the kernels' form)
 LDS_B128 = 176.7       # ds_read_b128 at 16-byte aligned addresses
@@ -301,7 +302,10 @@ SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8
                 (8, 4, 8, 32),
                 # byte-quad tile (D = 1 rows with whole channel quads)
                 (8, 4, 8, 64, 1), (8, 4, 16, 64, 1), (8, 2, 16, 64, 1), (4, 8, 8, 64, 1), (16, 2, 16, 64, 1),
-                (4, 4, 16, 64, 1), (4, 8, 16, 64, 1), (4, 8, 4, 64, 1)]
+                (4, 4, 16, 64, 1), (4, 8, 16, 64, 1), (4, 8, 4, 64, 1),
+                # byte-quad tile with 4 staging waves besides the summing ones
+                (4, 8, 8, 64, 2), (8, 4, 8, 64, 2), (4, 8, 12, 64, 2), (8, 4, 12, 64, 2), (4, 8, 4, 64, 2),
+                (8, 4, 4, 64, 2)]
 
 
 def shape_sweep(w):
@@ -490,6 +494,10 @@ def main():
                    "avg_launch_ms": v[1] / v[0],
                    ("adds_per_s" if k.startswith("dedisperse") else "bytes_per_s"): v[2] / (v[1] / 1e3)}
                for k, v in prof.items()}
+    kname = KERNEL_NAME[dom]
+    if dom == "dedisperse_quad":  # the byte-quad kernel of the rows' shapes (the D = 1 rows share one)
+        kinds = {sh[4] for sh in cfg["tile_shapes"] if sh[4] != 0}
+        kname = "/".join(QUAD_KERNEL_BY_KIND[k] for k in sorted(kinds))
     all_adds = sum(prof[k][2] for k in PEAK_SAMPLE_ADDS if k in prof)
     all_ms = sum(prof[k][1] for k in PEAK_SAMPLE_ADDS if k in prof)
     out = {
@@ -501,7 +509,7 @@ def main():
                      "frac": achieved / peak,
                      "traffic": measured_traffic(w.name) if dom == "dedisperse_quad" else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": KERNEL_NAME[dom], "launches_per_step": n / args.steps,
+                     "kernel": kname, "launches_per_step": n / args.steps,
                      "work": "integer sample additions (n_dm * n_out * nchan per launch)",
                      "peak_note": ("four 8-bit sample additions per v_sad_u8 lane operation: 4 x 256 CUs x 64 "
                                    "lanes x 2.4 GHz" if dom == "dedisperse_quad" else
@@ -511,7 +519,7 @@ def main():
                                   "staging them",
                      "all_dedispersion": {"adds_per_s": all_adds / (all_ms / 1e3), "ms_per_step": all_ms / args.steps,
                                           "what": "every dedispersion launch of the step (both tiles)"}},
-        "lds": {"what": f"LDS read bandwidth of {KERNEL_NAME[dom]}: {lds_b:g} byte(s) of staged samples per "
+        "lds": {"what": f"LDS read bandwidth of {kname}: {lds_b:g} byte(s) of staged samples per "
                         "sample addition, read as ds_read2st64_b32",
                 "achieved_TBps": lds_b * achieved / 1e12,
                 "peak_form_TBps": LDS_READ2ST64 * 256 * 2.4e9 / 1e12,

@@ -82,7 +82,7 @@ RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
       // the byte-quad default does not suit every row (delay spreads wider
       // than its LDS copies): such rows keep the 16-bit tile
       const bool tuned = ctx->tuned.count(row_signature(desc, s)) > 0;
-      if (e.status != GSP_EINVAL || want.kind != 1 || tuned) throw;
+      if (e.status != GSP_EINVAL || want.kind == 0 || tuned) throw;
       DedispShape pair = want;
       pair.kind = 0;
       pair.groups = 4;

@@ -170,8 +170,8 @@ DedispShape default_shape(int32_t D, int32_t nchan) {
   s.waves = 8;
   s.groups = 4;
   s.chunk = 32;
-  if (D == 1 && nchan % 4 == 0) {  // byte-quad tile
-    s.kind = 1;
+  if (D == 1 && nchan % 4 == 0) {  // byte-quad tile with staging waves
+    s.kind = 2;
     s.groups = 4;
     s.tpw = 8;
     s.chunk = 64;
@@ -180,7 +180,7 @@ DedispShape default_shape(int32_t D, int32_t nchan) {
 }
 
 bool shape_supported(const DedispShape &s) {
-  if (s.kind == 1) return quad_shape_supported(s);
+  if (s.kind == 1 || s.kind == 2) return quad_shape_supported(s);
   if (s.kind != 0) return false;
   const int kt = s.groups * 16 + s.tpw;
   const bool inst = kt == 8 * 16 + 4 || kt == 4 * 16 + 8 || kt == 4 * 16 + 4 || kt == 2 * 16 + 8;
@@ -210,7 +210,7 @@ static int flush_interval(int32_t D) {
 }
 
 int64_t staged_pitch(const RowTables &rt) {
-  if (rt.shape.kind == 1) return rt.q_pitch;
+  if (rt.shape.kind != 0) return rt.q_pitch;
   // furthest element a staging pass can touch: t0 + base + 2 * row_dw + 2
   const int64_t T = rt.shape.samples_per_block();
   const int64_t n_t = (rt.n_out + T - 1) / T;
@@ -226,7 +226,7 @@ void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
     rt.delays_host.resize((size_t)g.n_dm * desc->nchan);
     compute_delays(desc, freqs, s, rt.delays_host.data());
   }
-  if (shape.kind == 1) {
+  if (shape.kind != 0) {
     rt.n_dm = g.n_dm;
     rt.D = g.downsamp;
     rt.nchan = desc->nchan;
@@ -407,7 +407,7 @@ static void launch_k(const DedispArgs &a, int waves, int64_t lds, int D, hipStre
 }
 
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st) {
-  if (rt.shape.kind == 1) {
+  if (rt.shape.kind != 0) {
     launch_dedisp_quad(ctx, rt, out_row, st);
     return;
   }

@@ -239,6 +239,180 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
   }
 }
 
+// The same tile with the work split by waves: NP staging waves fill the
+// next pass's LDS buffer while the other waves sum the current one (all
+// waves meet at one barrier per pass).  The summing waves never wait for a
+// global load; the staging waves keep R chunks per thread in flight, their
+// copy records one batch ahead.
+__device__ __forceinline__ void wg_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int K, int TPW, int NP>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_dedisp_quad_pc(QuadArgs a) {
+  static_assert(TPW % 2 == 0 && TPW <= 8, "trials are read in pairs");
+  extern __shared__ __align__(16) uint32_t lds[];
+  const int G = a.n_dm_tiles * a.n_t_tiles;
+  const int L = xcd_remap(blockIdx.x, G);
+  const int dm_tile = L % a.n_dm_tiles, t_tile = L / a.n_dm_tiles;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int NC = (int)(blockDim.x >> 6) - NP;  // summing waves
+  constexpr int T = 64 * K;
+  const int t0 = t_tile * T;
+  const int p_first = a.tile_pass[dm_tile];
+  const int n_pass = a.tile_pass[dm_tile + 1] - p_first - 1;
+  auto data_buf = [&](int j) { return lds + (j & 1) * a.data_dw; };
+
+  int w0 = 0;
+  int4 win = make_int4(0, 0, 0, 0);
+  auto fetch_window = [&](int from) {
+    w0 = from;
+    win = a.passes[p_first + min(from + lane, n_pass)];
+  };
+  auto q_begin = [&](int j) { return __builtin_amdgcn_readlane(win.x, j - w0); };
+  auto c_begin = [&](int j) { return __builtin_amdgcn_readlane(win.y, j - w0); };
+  auto chunks_of = [&](int j) { return __builtin_amdgcn_readlane(win.z, j - w0); };
+  auto magic_of = [&](int j) { return (uint32_t)__builtin_amdgcn_readlane(win.w, j - w0); };
+  fetch_window(0);
+
+  if (wave >= NC) {
+    // ---- staging waves ----
+    constexpr int PT = 64 * NP;
+    constexpr int R = 4;  // chunks per thread in flight
+    const int ptid = tid - 64 * NC;
+    auto stage = [&](int j) {
+      const int cb = c_begin(j), CU = chunks_of(j);
+      const uint32_t M = magic_of(j);
+      const int nchk = (c_begin(j + 1) - cb) * CU;
+      const uint8_t *base = a.Y + (int64_t)(4 * q_begin(j)) * a.pitch;
+      uint4 *dst4 = reinterpret_cast<uint4 *>(data_buf(j));
+      int4 rec[R];
+      int tcs[R];
+      auto fetch_rec = [&](int g0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int g = min(g0 + r * PT, nchk - 1);  // clamped: loads stay in bounds
+          const int k = (int)__umulhi((uint32_t)g, M);
+          tcs[r] = t0 + 4 * (g + __mul24(k, -CU));
+          rec[r] = a.copies[cb + k];
+        }
+      };
+      fetch_rec(ptid);
+      for (int g0 = ptid; g0 < nchk; g0 += R * PT) {
+        uint32_t w[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int rv[4] = {rec[r].x, rec[r].y, rec[r].z, rec[r].w};
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch)
+            w[r][ch] = *reinterpret_cast<const u32_unaligned *>(base + (uint32_t)(rv[ch] + tcs[r]));
+        }
+        if (g0 + R * PT < nchk) fetch_rec(g0 + R * PT);  // the next batch's records in flight
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int g = g0 + r * PT;
+          if (g < nchk) {
+            const uint32_t x01l = __builtin_amdgcn_perm(w[r][1], w[r][0], 0x05010400u);
+            const uint32_t x01h = __builtin_amdgcn_perm(w[r][1], w[r][0], 0x07030602u);
+            const uint32_t x23l = __builtin_amdgcn_perm(w[r][3], w[r][2], 0x05010400u);
+            const uint32_t x23h = __builtin_amdgcn_perm(w[r][3], w[r][2], 0x07030602u);
+            dst4[g] = make_uint4(
+                __builtin_amdgcn_perm(x23l, x01l, 0x05040100u), __builtin_amdgcn_perm(x23l, x01l, 0x07060302u),
+                __builtin_amdgcn_perm(x23h, x01h, 0x05040100u), __builtin_amdgcn_perm(x23h, x01h, 0x07060302u));
+          }
+        }
+      }
+    };
+    stage(0);
+    wg_barrier();  // pass 0 staged
+    for (int kc = 0; kc < n_pass; ++kc) {
+      if (kc + 3 > w0 + 63) fetch_window(kc);
+      if (kc + 1 < n_pass) stage(kc + 1);  // into the buffer pass kc - 1 used
+      wg_barrier();                        // pass kc summed, pass kc + 1 staged
+    }
+    return;
+  }
+
+  // ---- summing waves: as in k_dedisp_quad ----
+  const int i_wave = dm_tile * TPW * NC + wave * TPW;
+  uint32_t roff[TPW / 2], noff[TPW / 2];
+  auto load_off = [&](int j) {
+    const int qb = q_begin(j), qe = q_begin(j + 1);
+    const uint32_t *o = a.addr + (int64_t)(qb + min(lane, qe - qb - 1)) * (a.n_dm_pad >> 1) + (i_wave >> 1);
+    if constexpr (TPW == 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(o);
+      noff[0] = v.x;
+      noff[1] = v.y;
+      noff[2] = v.z;
+      noff[3] = v.w;
+    } else if constexpr (TPW == 4) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(o);
+      noff[0] = v.x;
+      noff[1] = v.y;
+    } else {
+      noff[0] = o[0];
+    }
+  };
+  uint32_t acc[TPW][K];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[t][k] = 0;
+  const uint32_t *cur = lds;
+  auto ld = [&](int q, int t, uint32_t *v) {
+    const uint32_t pair = (uint32_t)__builtin_amdgcn_readlane((int)roff[t >> 1], q);
+    const uint32_t o = (t & 1) ? pair >> 16 : pair & 0xFFFFu;
+    const uint32_t *src = cur + o + lane;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = src[64 * k];
+  };
+  auto add = [&](const uint32_t *v, int t) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[t][k] = __builtin_amdgcn_sad_u8(v[k], 0u, acc[t][k]);
+  };
+  load_off(0);
+  wg_barrier();  // pass 0 staged
+  for (int kc = 0; kc < n_pass; ++kc) {
+    if (kc + 3 > w0 + 63) fetch_window(kc);
+#pragma unroll
+    for (int t = 0; t < TPW / 2; ++t) roff[t] = noff[t];
+    if (kc + 1 < n_pass) load_off(kc + 1);
+    cur = data_buf(kc);
+    const int last = q_begin(kc + 1) - q_begin(kc) - 1;
+    uint32_t va[K], vb[K];
+    ld(0, 0, va);
+    for (int q = 0; q <= last; ++q) {
+      const int qn = min(q + 1, last);
+#pragma unroll
+      for (int t = 0; t < TPW; t += 2) {
+        ld(q, t + 1, vb);
+        add(va, t);
+        if (t + 2 < TPW)
+          ld(q, t + 2, va);
+        else
+          ld(qn, 0, va);
+        add(vb, t + 1);
+      }
+    }
+    wg_barrier();  // pass kc summed, pass kc + 1 staged
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int i = i_wave + t;
+    if (i >= a.n_dm) break;
+    int32_t *orow = a.out + (int64_t)i * a.out_pitch;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t tt = (int64_t)t0 + lane + 64 * k;
+      if (tt < a.n_out) orow[tt] = (int32_t)acc[t][k];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -247,11 +421,16 @@ static constexpr int64_t kQuadLdsMax = 160 * 1024;
 static constexpr int kQuadPassMax = 64;               // quads per pass: one per lane for the offsets
 static constexpr int kQuadRecMax = 128;               // copies per pass (their records share the LDS)
 
+static constexpr int kQuadStagingWaves = 4;  // kind 2: staging waves besides the summing ones
+
 bool quad_shape_supported(const DedispShape &s) {
   const int kt = s.groups * 16 + s.tpw;
+  if (s.kind == 2)
+    return (kt == 8 * 16 + 4 || kt == 4 * 16 + 8) && s.waves >= 1 && s.waves + kQuadStagingWaves <= 16 &&
+           s.chunk >= 1;
   const bool inst = kt == 8 * 16 + 4 || kt == 8 * 16 + 2 || kt == 4 * 16 + 8 || kt == 16 * 16 + 2 ||
                     kt == 4 * 16 + 4;
-  return inst && s.waves >= 1 && s.waves <= 16 && s.chunk >= 1;
+  return s.kind == 1 && inst && s.waves >= 1 && s.waves <= 16 && s.chunk >= 1;
 }
 
 void quad_tables_host(const RowTables &rt, QuadHost &H) {
@@ -264,13 +443,14 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   const int n_tiles = (n_dm + MT - 1) / MT;
   const int n_dm_pad = n_tiles * MT;
   const int T = 64 * sh.groups;
+  const bool pc = sh.kind == 2;  // staging waves: no register or record limit on a pass
   const int threads = 64 * sh.waves;
-  const int64_t chunk_cap = (int64_t)quad_chunks(sh.groups, sh.tpw) * threads;  // staging chunks per pass
-  const int rec_cap = std::min(threads, kQuadRecMax);
-  // two buffers each of copies and records: two workgroups per CU up to 8
-  // waves, one (all 160 KB) above
+  const int64_t chunk_cap = pc ? INT32_MAX : (int64_t)quad_chunks(sh.groups, sh.tpw) * threads;  // chunks per pass
+  const int rec_cap = pc ? INT32_MAX : std::min(threads, kQuadRecMax);
+  // two buffers each of copies (and records): two workgroups per CU up to 8
+  // summing waves, one (all 160 KB) above
   const int64_t budget = sh.waves > 8 ? kQuadLdsMax : kQuadLdsBudget;
-  const int64_t dw_cap = (budget / 4 - 2 * 4 * (int64_t)rec_cap) / 2;  // LDS dwords of copies per pass
+  const int64_t dw_cap = (budget / 4 - (pc ? 0 : 2 * 4 * (int64_t)rec_cap)) / 2;  // LDS dwords of copies per pass
   const int64_t n_t = (rt.n_out + T - 1) / T;
   if ((n_t - 1) * T + rt.max_delay + dw_cap + 1024 >= (1LL << 30))
     fail(GSP_EINVAL, "row too long for the byte-quad tile's 32-bit offsets");
@@ -402,8 +582,8 @@ void build_quad_tables(gsp_ctx *ctx, RowTables &rt) {
   quad_tables_host(rt, H);
   rt.q_pitch = H.pitch;
   rt.data_dw = (int32_t)H.lds_dw;
-  rt.q_rec_dw = 4 * H.rec_max;
-  rt.lds_bytes = 2 * (H.lds_dw + 4 * (int64_t)H.rec_max) * 4;
+  rt.q_rec_dw = rt.shape.kind == 2 ? 0 : 4 * H.rec_max;
+  rt.lds_bytes = 2 * (H.lds_dw + rt.q_rec_dw) * 4;
   rt.q_staged_dw = H.staged;
   rt.max_chunk = H.max_q;
   rt.shape.chunk = H.max_q;
@@ -425,6 +605,15 @@ static void launch_q(const QuadArgs &a, int waves, int64_t lds, hipStream_t st) 
   check_hip(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
             "set LDS size");
   hipLaunchKernelGGL(kern, dim3(a.n_dm_tiles * a.n_t_tiles), dim3(64 * waves), (size_t)lds, st, a);
+}
+
+template <int K, int TPW>
+static void launch_qpc(const QuadArgs &a, int waves, int64_t lds, hipStream_t st) {
+  auto kern = k_dedisp_quad_pc<K, TPW, kQuadStagingWaves>;
+  check_hip(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+            "set LDS size");
+  hipLaunchKernelGGL(kern, dim3(a.n_dm_tiles * a.n_t_tiles), dim3(64 * (waves + kQuadStagingWaves)), (size_t)lds, st,
+                     a);
 }
 
 void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st) {
@@ -451,6 +640,15 @@ void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hip
   if ((int64_t)a.n_dm_tiles * n_t >= (1LL << 31)) fail(GSP_EOVERFLOW, "too many dedispersion tiles");
   a.n_t_tiles = (int32_t)n_t;
   ProfScope prof(ctx, "dedisperse_quad", st, (double)rt.n_dm * (double)rt.n_out * (double)rt.nchan);
+  if (sh.kind == 2) {
+    switch (sh.groups * 16 + sh.tpw) {
+      case 8 * 16 + 4: launch_qpc<8, 4>(a, sh.waves, rt.lds_bytes, st); break;
+      case 4 * 16 + 8: launch_qpc<4, 8>(a, sh.waves, rt.lds_bytes, st); break;
+      default: fail(GSP_EINVAL, "unsupported dedispersion shape");
+    }
+    check_hip(hipGetLastError(), "launch dedispersion kernel");
+    return;
+  }
   switch (sh.groups * 16 + sh.tpw) {
     case 8 * 16 + 4: launch_q<8, 4>(a, sh.waves, rt.lds_bytes, st); break;
     case 8 * 16 + 2: launch_q<8, 2>(a, sh.waves, rt.lds_bytes, st); break;

@@ -41,10 +41,11 @@ struct DedispShape {
   int waves = 8;     // waves per block
   int groups = 8;    // dword groups per lane (samples per block = 128 * groups)
   int chunk = 32;    // channels staged per pass (kind 1: channel quads per pass)
-  int kind = 0;      // 0: 16-bit pair tile (any row); 1: byte-quad tile (D = 1, nchan % 4 == 0)
+  int kind = 0;      // 0: 16-bit pair tile (any row); 1: byte-quad tile (D = 1, nchan % 4 == 0);
+                     // 2: byte-quad tile with 4 staging waves besides `waves` summing waves
   int trials_per_block() const { return tpw * waves; }
-  // kind 0: a lane sums `groups` dwords of two samples; kind 1: `groups` dwords of one sample
-  int samples_per_block() const { return (kind == 1 ? 64 : 128) * groups; }
+  // kind 0: a lane sums `groups` dwords of two samples; kinds 1, 2: `groups` dwords of one sample
+  int samples_per_block() const { return (kind != 0 ? 64 : 128) * groups; }
 };
 
 // Per-row device tables for one plan (cached by plan key).

@@ -31,7 +31,9 @@ def _run(env, w, X=None):
         X = w.generate()
     fb = torch.from_numpy(X).to("cuda")
     desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
-    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    # a sentinel in every output: an output no tile writes cannot pass
+    out = torch.full((desc.total,), -1, dtype=torch.int32, device="cuda")
+    dmt = ctx.dedisperse(fb, w.freqs, desc, out=out)
     torch.cuda.synchronize()
     return X, desc, dmt
 

@@ -12,10 +12,12 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 8, 16), (4, 4, 8, 32), (4, 8, 4, 16), (4, 8, 4, 32), (2, 8, 8, 16), (2, 8, 4, 32),
           (4, 4, 4, 16), (8, 4, 8, 16), (4, 4, 1, 3), (2, 8, 1, 1)]
-# byte-quad tile (groups, tpw, waves, quads per pass, kind 1): the autotuner's
-# candidates, one-quad and three-quad passes, a single wave
+# byte-quad tile (groups, tpw, waves, quads per pass, kind): the autotuner's
+# candidates, one-quad and three-quad passes, a single summing wave
 QUAD_SHAPES = [(8, 4, 8, 64, 1), (8, 4, 16, 64, 1), (8, 2, 16, 64, 1), (8, 2, 8, 64, 1), (4, 8, 8, 64, 1),
-               (16, 2, 16, 64, 1), (4, 4, 8, 64, 1), (8, 4, 16, 3, 1), (8, 4, 8, 1, 1), (8, 2, 1, 64, 1)]
+               (16, 2, 16, 64, 1), (4, 4, 8, 64, 1), (8, 4, 16, 3, 1), (8, 4, 8, 1, 1), (8, 2, 1, 64, 1),
+               # kind 2: 4 staging waves besides `waves` summing waves
+               (4, 8, 8, 64, 2), (8, 4, 8, 64, 2), (4, 8, 12, 64, 2), (4, 8, 1, 64, 2), (8, 4, 8, 3, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +41,8 @@ def test_shape_bit_exact(case, shape):
     say(f"[case] shape {shape}")
     for s in range(desc.n_seg):
         ctx.set_row_shape(w.freqs, desc, s, *shape)
-    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    # a sentinel in every output: an output no tile writes cannot pass
+    dmt = ctx.dedisperse(fb, w.freqs, desc, out=torch.full((desc.total,), -1, dtype=torch.int32, device="cuda"))
     views = gsp.segment_views(desc, dmt)
     for s in range(desc.n_seg):
         assert (views[s].cpu().numpy() == ref[s]).all(), (shape, s)
@@ -75,7 +78,7 @@ def quad_case(dev):
 
 def test_quad_is_default_for_d1(quad_case):
     gsp, ctx, w, fb, desc, ref, torch = quad_case
-    assert ctx.row_shape(w.freqs, desc, 0)[4] == 1
+    assert ctx.row_shape(w.freqs, desc, 0)[4] == 2
     assert ctx.row_shape(w.freqs, desc, 1)[4] == 0
     with pytest.raises(gsp.GspError):  # D = 2 rows are summed as 16-bit samples
         ctx.set_row_shape(w.freqs, desc, 1, 8, 4, 8, 64, 1)
@@ -87,8 +90,8 @@ def test_quad_shape_bit_exact(quad_case, shape):
     say(f"[case] quad shape {shape}")
     ctx.set_row_shape(w.freqs, desc, 0, *shape)
     used = ctx.row_shape(w.freqs, desc, 0)
-    assert used[4] == 1 and used[3] <= shape[3], used
-    dmt = ctx.dedisperse(fb, w.freqs, desc)
+    assert used[4] == shape[4] and used[3] <= shape[3], used
+    dmt = ctx.dedisperse(fb, w.freqs, desc, out=torch.full((desc.total,), -1, dtype=torch.int32, device="cuda"))
     views = gsp.segment_views(desc, dmt)
     for s in range(desc.n_seg):
         assert (views[s].cpu().numpy() == ref[s]).all(), (shape, s)
