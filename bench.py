@@ -63,24 +63,26 @@ def describe(w, desc):
     }
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_quad_realistic_traffic.md")
-DEDISP_SOURCES = [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_quad.hip")]  # the kernel's device code
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_realistic_traffic.md")
+# the device code of each dedispersion tile, by its profile key
+KERNEL_SOURCES = {"k_dedisp_quad": [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_quad.hip")],
+                  "k_dedisp": [os.path.join(ROOT, "paper_2110_12749_amd", "csrc", "dedisp_tile.h")]}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(key: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in DEDISP_SOURCES:
+    for f in KERNEL_SOURCES[key]:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload_name: str):
-    """HBM bytes per launch of the byte-quad dedispersion kernel (the D = 1
-    row) from the committed rocprofv3 counter summary (FETCH_SIZE +
+def measured_traffic(workload_name: str, key: str):
+    """HBM bytes per launch of a dedispersion tile (key "k_dedisp_quad" or
+    "k_dedisp") from the committed rocprofv3 counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy kernel), or None when there is none for
-    this workload or the kernel source changed since."""
+    this workload or the kernel's source changed since."""
     if workload_name != "realistic" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -89,10 +91,10 @@ def measured_traffic(workload_name: str):
             if ":" in line and not line.startswith(("#", "|", " ")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get(key + ".source_sha256") != kernel_source_hash(key):
         return None
     try:
-        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+        return float(kv[key + ".fetch_bytes_per_launch"]) + float(kv[key + ".write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -507,7 +509,7 @@ def main():
         "rtf": rtf,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(w.name) if dom == "dedisperse_quad" else None,
+                     "traffic": measured_traffic(w.name, "k_dedisp_quad" if dom == "dedisperse_quad" else "k_dedisp"),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": kname, "launches_per_step": n / args.steps,
                      "work": "integer sample additions (n_dm * n_out * nchan per launch)",
