@@ -109,3 +109,28 @@ def test_quad_shape_rejected_when_copies_do_not_fit(quad_case):
     dmt = ctx.dedisperse(fb, w.freqs, desc)
     views = gsp.segment_views(desc, dmt)
     assert (views[0].cpu().numpy() == ref[0]).all()
+
+
+@pytest.mark.parametrize("nchan,nsamp,tsamp,seg,kind", [
+    (4, 3000, 196.608e-6, (0.0, 1.0, 3, 1), 2),      # one channel quad
+    (8, 5000, 98.304e-6, (0.0, 0.5, 1, 1), 2),       # two quads, a single trial
+    (12, 4097, 98.304e-6, (5.0, 0.7, 70, 1), 0),     # quad copies too wide: the 16-bit tile
+])
+def test_quad_default_on_few_channels(dev, nchan, nsamp, tsamp, seg, kind):
+    """The D = 1 default on very few channels: the byte-quad tile where its
+    copies fit, else the 16-bit tile; bit-exact either way."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    w = synth.small(nchan=nchan, nsamp=nsamp, segments=[seg], tsamp=tsamp, n_pulses=1)
+    X = w.generate()
+    ref = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    ctx = gsp.Context(0)
+    try:
+        assert ctx.row_shape(w.freqs, desc, 0)[4] == kind
+        fb = torch.from_numpy(X).to("cuda")
+        dmt = ctx.dedisperse(fb, w.freqs, desc, out=torch.full((desc.total,), -1, dtype=torch.int32, device="cuda"))
+        assert (gsp.segment_views(desc, dmt)[0].cpu().numpy() == ref[0]).all()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
