@@ -497,7 +497,9 @@ int gsp_profile_read(gsp_ctx *ctx, gsp_kernel_stat *out, int32_t cap, int32_t *n
  * output for this filterbank).  cands_dev: device gsp_candidate[n] (as
  * returned by the search, copied to the device); a candidate whose row,
  * trial or box end lies outside the plan gets two zero images.  out_dev: device
- * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`.  The context keeps
+ * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`.  Trial means are
+ * computed only for the trials of images whose first bin starts before the
+ * data (a pass over those rows alone).  The context keeps
  * a device buffer of 16 KB per candidate for the frequency-time band sums
  * (grown, with a device synchronisation, when a call has more candidates
  * than any before it). */

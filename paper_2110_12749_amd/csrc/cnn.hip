@@ -765,6 +765,30 @@ __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
   }
 }
 
+// The trials whose means a batch of cutouts reads: the 64 trials of an
+// event's DM-time image when its first bin starts before the series does
+// (those bins count as the trial's mean).  One thread per (event, image row).
+__global__ void k_cutout_need(CutoutArgs a, uint32_t *__restrict__ need, int32_t n_trials) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n_trials) need[u] = 0;
+}
+__global__ void k_cutout_mark(CutoutArgs a, uint32_t *__restrict__ need) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= a.n * 64) return;
+  const gsp_candidate c = a.cand[u / 64];
+  const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
+                  c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
+                  c.t_peak + c.width - 1 < a.row[c.seg].n_out;
+  if (!ok) return;
+  const CutRow R = a.row[c.seg];
+  const int64_t e = c.t_peak + c.width - 1;
+  const int r = max(1, min(a.rmax, c.width / 8));
+  if (e - 64 * (int64_t)r + 1 >= 0) return;  // every bin starts inside the series
+  const int lo = max(0, min(c.dm_index - 32, R.n_dm - 64));
+  const int tr = lo + (int)(u % 64);
+  if (tr < R.n_dm) need[R.trial0 + tr] = 1;
+}
+
 __global__ __launch_bounds__(256) void k_cutout(CutoutArgs a) {
   __shared__ double img[2][64 * 64];
   __shared__ double red[3][256];
@@ -1321,11 +1345,9 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     if (desc->kind != 0) fail(GSP_EINVAL, "cutouts take a brute-force plan's output");
     if (n == 0) return;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    launch_stats(ctx, dmt, desc, st);  // per-trial means for padding before the start
     CutoutArgs a;
     std::memset(&a, 0, sizeof(a));
     a.fb = fb;
-    a.musig = ctx->stats.as<double>();
     a.cand = cands;
     a.n = n;
     a.nchan = desc->nchan;
@@ -1349,6 +1371,16 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
       a.row[s].D = desc->seg[s].downsamp;
       a.row[s].trial0 = desc->trial0[s];
     }
+    // per-trial means for the bins before the start, of the trials read only
+    ctx->need.device = ctx->device;
+    ctx->need.reserve((size_t)desc->n_trials * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_cutout_need, dim3((unsigned)((desc->n_trials + 255) / 256)), dim3(256), 0, st, a,
+                       ctx->need.as<uint32_t>(), desc->n_trials);
+    hipLaunchKernelGGL(k_cutout_mark, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, st, a,
+                       ctx->need.as<uint32_t>());
+    check_hip(hipGetLastError(), "launch cutout trial marks");
+    launch_stats(ctx, dmt, desc, st, ctx->need.as<uint32_t>());
+    a.musig = ctx->stats.as<double>();
     ctx->ftsums.device = ctx->device;
     ctx->ftsums.reserve((size_t)n * 64 * 64 * sizeof(uint32_t));
     a.ftsums = ctx->ftsums.as<uint32_t>();

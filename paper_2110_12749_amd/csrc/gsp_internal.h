@@ -149,6 +149,7 @@ struct gsp_ctx {
   gsp::DevBuf widths;      // device copy of the width set
   gsp::DevBuf jobs;        // device copy of the series-job table
   gsp::DevBuf ftsums;      // frequency-time band sums of batch cutouts
+  gsp::DevBuf need;        // per trial: whether batch cutouts read its mean
   gsp::DevBuf rfi;         // RFI mitigation: spectrum sums, flags, block means
   gsp::DevBuf zbuf;        // sub-band series of sub-band dedispersion
   std::map<std::string, std::shared_ptr<gsp::SubbandPlan>> subband;
@@ -235,14 +236,17 @@ void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hip
 SearchTiling search_tiling(int32_t max_width);
 void set_search_attributes(const SearchTiling &tl);
 void finalize_table(SeriesTable &t, const SearchTiling &tl);
+// Per-trial mean and sigma of every series of the table; with `need`, only
+// of the trials g with need[g] != 0 (the others keep their old values).
 void launch_stats_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, double *musig, double bytes,
-                        hipStream_t st);
+                        hipStream_t st, const uint32_t *need = nullptr);
 void launch_search_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, const SearchTiling &tl,
                          const double *musig, const int32_t *widths_dev, int32_t n_widths, int32_t max_width,
                          float thr, Frag *frags, int64_t cap, unsigned long long *counter, double bytes,
                          hipStream_t st);
 
-void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st);
+void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st,
+                  const uint32_t *need = nullptr);
 // Sub-band dedispersion (subband.hip)
 void subband_plan_shape(int64_t nsamp, int32_t nchan, const double *freqs, double tsamp, const gsp_segment *segs,
                         int32_t n_seg, const int32_t *n_sub, const int32_t *group, gsp_dmt_desc *desc);

@@ -60,11 +60,13 @@ __device__ __forceinline__ int find_job_by_item(const SeriesTable *t, int64_t b)
 static constexpr int kStatsThreads = 256;
 
 __global__ __launch_bounds__(kStatsThreads) void k_stats(const SeriesTable *__restrict__ tb,
-                                                          double *__restrict__ musig) {
+                                                          double *__restrict__ musig,
+                                                          const uint32_t *__restrict__ need) {
   __shared__ int64_t r1[kStatsThreads];
   __shared__ unsigned __int128 r2[kStatsThreads];
   const int n_trials = tb->n_trials;
   for (int g = blockIdx.x; g < n_trials; g += gridDim.x) {
+    if (need && need[g] == 0) continue;  // a trial nobody reads: left as it was
     const SeriesJob &J = tb->job[find_job_by_trial(tb, g)];
     const int64_t n = J.n;
     const int32_t *x = J.x + (int64_t)(g - J.trial0) * J.pitch + J.e_begin;
@@ -488,10 +490,10 @@ void finalize_table(SeriesTable &t, const SearchTiling &tl) {
 }
 
 void launch_stats_table(gsp_ctx *ctx, const SeriesTable *tb_dev, int64_t grid, double *musig, double bytes,
-                        hipStream_t st) {
+                        hipStream_t st, const uint32_t *need) {
   if (grid <= 0) return;
   ProfScope prof(ctx, "stats", st, bytes);
-  hipLaunchKernelGGL(k_stats, dim3((unsigned)grid), dim3(kStatsThreads), 0, st, tb_dev, musig);
+  hipLaunchKernelGGL(k_stats, dim3((unsigned)grid), dim3(kStatsThreads), 0, st, tb_dev, musig, need);
   check_hip(hipGetLastError(), "launch statistics kernel");
 }
 
@@ -548,15 +550,18 @@ static SeriesTable *upload_table(gsp_ctx *ctx, const SeriesTable &t, hipStream_t
   return ctx->jobs.as<SeriesTable>();
 }
 
-void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st) {
+void launch_stats(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc *desc, hipStream_t st,
+                  const uint32_t *need) {
   ctx->stats.device = ctx->device;
   ctx->stats.reserve((size_t)desc->n_trials * 2 * sizeof(double));
   SeriesTable t;
   batch_table(desc, dmt, t);
   finalize_table(t, search_tiling(1));
   SeriesTable *d = upload_table(ctx, t, st);
-  // bytes: the int32 DM-time array read once
-  launch_stats_table(ctx, d, t.n_trials, ctx->stats.as<double>(), 4.0 * (double)desc->total, st);
+  // bytes: the int32 DM-time array read once (the selected trials' rows only
+  // when `need` is given; not known on the host then)
+  launch_stats_table(ctx, d, t.n_trials, ctx->stats.as<double>(), need ? 0.0 : 4.0 * (double)desc->total, st,
+                     need);
 }
 
 const double *stats_musig(gsp_ctx *ctx, const gsp_dmt_desc *) { return ctx->stats.as<double>(); }
