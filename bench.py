@@ -520,7 +520,12 @@ def main():
                                   "; the kernel is bound by its LDS reads (see 'lds') and the VALU work of "
                                   "staging them",
                      "all_dedispersion": {"adds_per_s": all_adds / (all_ms / 1e3), "ms_per_step": all_ms / args.steps,
-                                          "what": "every dedispersion launch of the step (both tiles)"}},
+                                          "what": "every dedispersion launch of the step (both tiles)"},
+                     "int32_reference": {"peak": PEAK_INT32_OPS / 1e12, "frac": achieved / PEAK_INT32_OPS,
+                                         "all_dedispersion_frac": all_adds / (all_ms / 1e3) / PEAK_INT32_OPS,
+                                         "what": "against one 32-bit add per VALU lane and clock (256 CUs x 64 "
+                                                 "lanes x 2.4 GHz), the rate of a tile that adds one sample per "
+                                                 "lane operation; above 1 where samples are packed"}},
         "lds": {"what": f"LDS read bandwidth of {kname}: {lds_b:g} byte(s) of staged samples per "
                         "sample addition, read as ds_read2st64_b32",
                 "achieved_TBps": lds_b * achieved / 1e12,
