@@ -442,10 +442,16 @@ def main():
         raw = fb
         fb = torch.empty_like(raw)
 
-    def step():
+    def step(src=None):
+        # src: the device copy of the input this step reads (default: fb, or
+        # raw with RFI mitigation, which cleans it into fb)
+        fin = fb
         if raw is not None:
-            ctx.rfi_clean(raw, args.clip_sigma, 2048, zero_dm=True, out=fb, count=False, stream=stream)
-        ctx.dedisperse(fb, w.freqs, desc, out=dmt, stream=stream)
+            ctx.rfi_clean(raw if src is None else src, args.clip_sigma, 2048, zero_dm=True, out=fb, count=False,
+                          stream=stream)
+        elif src is not None:
+            fin = src
+        ctx.dedisperse(fin, w.freqs, desc, out=dmt, stream=stream)
         c = ctx.single_pulse_search(dmt, desc, w.widths, w.threshold, stream=stream)
         rep, ng = gsp.group_candidates(c)
         if net is not None and ng:
@@ -455,7 +461,7 @@ def main():
             keep = 0
             for e0 in range(0, len(ev), cut.shape[0]):
                 part = ev[e0:e0 + cut.shape[0]]
-                x = gsp.cutouts(ctx, fb, w.freqs, dmt, desc, part, out=cut[:len(part)], stream=stream)
+                x = gsp.cutouts(ctx, fin, w.freqs, dmt, desc, part, out=cut[:len(part)], stream=stream)
                 net.forward(x, out=logits[:len(part)], stream=stream)
                 keep += int((logits[:len(part)] > 0).sum().item())
             assert len(ev) == ng
@@ -563,12 +569,46 @@ def main():
             step()
         torch.cuda.synchronize()
         e2e = (time.perf_counter() - t) / args.e2e_steps
-        del Xp
+        # pipelined: the next input is copied on a second stream (default
+        # priority) into the other of two device buffers while the current
+        # step runs; a step waits for its copy, a copy for the step that last
+        # read its buffer
+        bufs = [dst, torch.empty_like(dst)]
+        cs = torch.cuda.Stream()
+        ready = [torch.cuda.Event(), torch.cuda.Event()]
+        free = [torch.cuda.Event(), torch.cuda.Event()]
+        for e in free:
+            e.record(stream)
+
+        def enqueue_copy(k):
+            b = k % 2
+            cs.wait_event(free[b])
+            with torch.cuda.stream(cs):
+                bufs[b].copy_(Xp, non_blocking=True)
+            ready[b].record(cs)
+
+        n_pipe = max(args.e2e_steps, 6)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        enqueue_copy(0)
+        for k in range(n_pipe):
+            if k + 1 < n_pipe:
+                enqueue_copy(k + 1)
+            stream.wait_event(ready[k % 2])
+            step(bufs[k % 2])
+            free[k % 2].record(stream)
+        torch.cuda.synchronize()
+        pipe = (time.perf_counter() - t) / n_pipe
+        del Xp, bufs
         out["end_to_end"] = {"ms_per_step": e2e * 1e3, "value": cfg["dm_trial_samples"] / e2e,
                              "rtf": (w.nsamp * w.tsamp) / e2e, "h2d_ms": h2d * 1e3,
                              "h2d_GBps": w.nsamp * w.nchan / h2d / 1e9, "steps": args.e2e_steps,
                              "what": "host-to-device copy of the uint8 input from pinned memory + the step "
-                                     "(candidates to the host included)"}
+                                     "(candidates to the host included)",
+                             "pipelined": {"ms_per_step": pipe * 1e3, "value": cfg["dm_trial_samples"] / pipe,
+                                           "rtf": (w.nsamp * w.tsamp) / pipe, "steps": n_pipe,
+                                           "what": "the same, with each step's input copied on a second stream "
+                                                   "while the previous step runs (two device input buffers)"}}
     if args.subband:
         out["subband"] = bench_subband(ctx, w, fb, stream, args.steps)
     del dmt
