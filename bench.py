@@ -36,7 +36,7 @@ PEAK_SAMPLE_ADDS = {"dedisperse": 2 * PEAK_INT32_OPS, "dedisperse_quad": 4 * PEA
 # samples, or four channels' bytes)
 LDS_BYTES_PER_ADD = {"dedisperse": 2.0, "dedisperse_quad": 1.0}
 KERNEL_NAME = {"dedisperse": "k_dedisp", "dedisperse_quad": "k_dedisp_quad"}
-QUAD_KERNEL_BY_KIND = {1: "k_dedisp_quad", 2: "k_dedisp_quad_pc"}  # the byte-quad tile's kernels by shape kind
+QUAD_KERNEL_BY_KIND = {1: "k_dedisp_quad", 2: "k_dedisp_quad_pc", 3: "k_dedisp_quad_pc"}  # byte-quad kernels by shape kind
 # LDS read rates measured on the MI355X for the kernels' access pattern, B/clk/CU
 LDS_READ2ST64 = 110.2  # ds_read2st64_b32, offsets from registers (the kernels' form)
 LDS_B128 = 176.7       # ds_read_b128 at 16-byte aligned addresses
@@ -307,6 +307,8 @@ SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8
                 (4, 4, 16, 64, 1), (4, 8, 16, 64, 1), (4, 8, 4, 64, 1),
                 # byte-quad tile with 4 staging waves besides the summing ones
                 (4, 8, 8, 64, 2), (8, 4, 8, 64, 2), (4, 8, 12, 64, 2), (8, 4, 12, 64, 2), (4, 8, 4, 64, 2),
+                # split rows: kind 2 over the channels whose copies fit, the 16-bit tile over the rest
+                (4, 8, 8, 64, 3), (4, 8, 12, 64, 3), (8, 4, 8, 64, 3),
                 (8, 4, 4, 64, 2)]
 
 

@@ -423,15 +423,24 @@ int gsp_stream_set_fragment_capacity(gsp_stream *s, int64_t cap);
  * 4 channels): a wave covers 64*`groups` output samples; LDS dwords hold the
  * bytes of 4 neighbouring channels, one staged copy per distinct pattern of
  * delay differences inside the quad over a tile of trials; at most `chunk`
- * (<= 64) quads per pass.  The default is kind 1 where it applies and its
- * copies fit, else kind 0.  gsp_row_shape reports the longest pass in
- * `chunk`. */
+ * (<= 64) quads per pass.  kind 2: the byte-quad tile with 4 more waves per
+ * workgroup that stage the next pass while the `waves` summing waves add
+ * the current one.  kind 3: a split row, for bands whose lowest (or
+ * highest) channels have delay copies too wide for the byte-quad tile: kind
+ * 2 with this shape over the channels whose copies fit, the 16-bit tile with
+ * shape (4, 4, 8, 32) over the run of channels at the end of the band that
+ * holds every quad that does not fit, both summed into the same outputs;
+ * GSP_EINVAL where every quad fits or those quads are not at one end.  The
+ * default for D = 1 rows with a multiple of 4 channels is kind 2 (4, 8, 8,
+ * 64) where its copies fit, else kind 3 where it applies, else kind 0 (4, 4,
+ * 8, 32); for other rows kind 0 (4, 4, 8, 32).  gsp_row_shape reports the
+ * longest pass in `chunk` (of the byte-quad part for kind 3). */
 typedef struct gsp_shape {
-  int32_t groups; /* kind 0: 2, 4 or 8; kind 1: 4, 8 or 16 */
-  int32_t tpw;    /* kind 0: 4 or 8; kind 1: 2, 4 or 8 */
-  int32_t waves;  /* kind 0: 1 .. 8; kind 1: 1 .. 16 */
+  int32_t groups; /* kind 0: 2, 4 or 8; kind 1: 4, 8 or 16; kinds 2, 3: 4 or 8 */
+  int32_t tpw;    /* kind 0: 4 or 8; kind 1: 2, 4 or 8; kinds 2, 3: 8 (groups 4) or 4 (groups 8) */
+  int32_t waves;  /* kind 0: 1 .. 8; kind 1: 1 .. 16; kinds 2, 3: 1 .. 12 summing waves */
   int32_t chunk;  /* >= 1 */
-  int32_t kind;   /* 0: 16-bit tile, 1: byte-quad tile */
+  int32_t kind;   /* 0: 16-bit tile, 1: byte-quad tile, 2: with staging waves, 3: split row */
 } gsp_shape;
 
 /* Autotuner.  For every plan row of `desc`, times the dedispersion kernel

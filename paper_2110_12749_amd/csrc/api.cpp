@@ -80,17 +80,29 @@ RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
       build_row_tables(ctx, desc, freqs, s, want, *rt);
     } catch (const Error &e) {
       // the byte-quad default does not suit every row (delay spreads wider
-      // than its LDS copies): such rows keep the 16-bit tile
+      // than its LDS copies): such rows split their band between the two
+      // tiles where the quads that do not fit lie at one end of it, else
+      // keep the 16-bit tile
       const bool tuned = ctx->tuned.count(row_signature(desc, s)) > 0;
-      if (e.status != GSP_EINVAL || want.kind == 0 || tuned) throw;
-      DedispShape pair = want;
-      pair.kind = 0;
-      pair.groups = 4;
-      pair.chunk = 32;
+      if (e.status != GSP_EINVAL || want.kind != 2 || tuned) throw;
       std::vector<int32_t> delays = std::move(rt->delays_host);
       rt = std::make_unique<RowTables>();
-      rt->delays_host = std::move(delays);
-      build_row_tables(ctx, desc, freqs, s, pair, *rt);
+      rt->delays_host = delays;
+      DedispShape split = want;
+      split.kind = 3;
+      try {
+        build_row_tables(ctx, desc, freqs, s, split, *rt);
+      } catch (const Error &e2) {
+        if (e2.status != GSP_EINVAL) throw;
+        DedispShape pair = want;
+        pair.kind = 0;
+        pair.groups = 4;
+        pair.tpw = 4;
+        pair.chunk = 32;
+        rt = std::make_unique<RowTables>();
+        rt->delays_host = std::move(delays);
+        build_row_tables(ctx, desc, freqs, s, pair, *rt);
+      }
     }
     rt->req = want;
     slot = std::move(rt);

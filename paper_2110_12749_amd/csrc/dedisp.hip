@@ -180,7 +180,7 @@ DedispShape default_shape(int32_t D, int32_t nchan) {
 }
 
 bool shape_supported(const DedispShape &s) {
-  if (s.kind == 1 || s.kind == 2) return quad_shape_supported(s);
+  if (s.kind >= 1 && s.kind <= 3) return quad_shape_supported(s);
   if (s.kind != 0) return false;
   const int kt = s.groups * 16 + s.tpw;
   const bool inst = kt == 8 * 16 + 4 || kt == 4 * 16 + 8 || kt == 4 * 16 + 4 || kt == 2 * 16 + 8;
@@ -210,6 +210,7 @@ static int flush_interval(int32_t D) {
 }
 
 int64_t staged_pitch(const RowTables &rt) {
+  if (rt.pitch_override > 0) return rt.pitch_override;
   if (rt.shape.kind != 0) return rt.q_pitch;
   // furthest element a staging pass can touch: t0 + base + 2 * row_dw + 2
   const int64_t T = rt.shape.samples_per_block();
@@ -408,14 +409,16 @@ static void launch_k(const DedispArgs &a, int waves, int64_t lds, int D, hipStre
 
 void launch_dedisp(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st) {
   if (rt.shape.kind != 0) {
+    // a split row: the 16-bit tile's channels first, the byte-quad tile adds
+    if (rt.shape.kind == 3) launch_dedisp(ctx, *rt.low, out_row, st);
     launch_dedisp_quad(ctx, rt, out_row, st);
     return;
   }
   const DedispShape &sh = rt.shape;
   DedispArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.Y = ctx->staged.ptr;
   a.pitch = staged_pitch(rt);
+  a.Y = static_cast<const uint8_t *>(ctx->staged.ptr) + (int64_t)rt.y_ch0 * a.pitch * (rt.D == 1 ? 1 : 2);
   a.addr = rt.addr.as<uint32_t>();
   a.base = rt.dmin.as<int32_t>();
   a.out = out_row;

@@ -50,6 +50,7 @@ struct QuadArgs {
   int32_t n_dm, n_dm_pad, n_dm_tiles, n_t_tiles;
   int32_t data_dw;           // LDS dwords of one buffer of staged copies (a multiple of 4)
   int32_t rec_dw;            // LDS dwords of one buffer of copy records (a multiple of 4)
+  int32_t accumulate;        // add the sums to what out holds (the other part of a split row)
 };
 
 // Staging chunks per thread and pass (registers: 4 per chunk)
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(1024) void k_dedisp_quad(QuadArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int64_t tt = (int64_t)t0 + lane + 64 * k;
-      if (tt < a.n_out) orow[tt] = (int32_t)acc[t][k];
+      if (tt < a.n_out) orow[tt] = (int32_t)acc[t][k] + (a.accumulate ? orow[tt] : 0);
     }
   }
 }
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int64_t tt = (int64_t)t0 + lane + 64 * k;
-      if (tt < a.n_out) orow[tt] = (int32_t)acc[t][k];
+      if (tt < a.n_out) orow[tt] = (int32_t)acc[t][k] + (a.accumulate ? orow[tt] : 0);
     }
   }
 }
@@ -422,10 +423,14 @@ static constexpr int kQuadPassMax = 64;               // quads per pass: one per
 static constexpr int kQuadRecMax = 128;               // copies per pass (their records share the LDS)
 
 static constexpr int kQuadStagingWaves = 4;  // kind 2: staging waves besides the summing ones
+// kind 3: quads whose staged copies exceed this fraction of the dwords their
+// trials read go to the 16-bit tile with those that do not fit (a pass of
+// such quads keeps the summing waves waiting for its staging)
+static constexpr double kQuadSplitStaged = 0.25;
 
 bool quad_shape_supported(const DedispShape &s) {
   const int kt = s.groups * 16 + s.tpw;
-  if (s.kind == 2)
+  if (s.kind == 2 || s.kind == 3)
     return (kt == 8 * 16 + 4 || kt == 4 * 16 + 8) && s.waves >= 1 && s.waves + kQuadStagingWaves <= 16 &&
            s.chunk >= 1;
   const bool inst = kt == 8 * 16 + 4 || kt == 8 * 16 + 2 || kt == 4 * 16 + 8 || kt == 16 * 16 + 2 ||
@@ -433,7 +438,90 @@ bool quad_shape_supported(const DedispShape &s) {
   return s.kind == 1 && inst && s.waves >= 1 && s.waves <= 16 && s.chunk >= 1;
 }
 
-void quad_tables_host(const RowTables &rt, QuadHost &H) {
+// The distinct delay patterns of quad q over the trials [i0, i0 + MT) (the
+// last trial repeated past n_dm): pattern k = delay differences (d1, d2, d3)
+// of channels 4q+1..3 from channel 4q, with the range [lo, hi] of the first
+// channel's delay over its trials; pat_of[j] = the pattern of trial i0 + j.
+struct QuadPat {
+  int32_t d1, d2, d3, lo, hi;
+};
+template <class DELAY>
+static void quad_patterns(DELAY delay, int i0, int MT, int q, std::vector<QuadPat> &P, uint8_t *pat_of) {
+  P.clear();
+  for (int j = 0; j < MT; ++j) {
+    const int i = i0 + j;
+    const int32_t o0 = delay(i, 4 * q), d1 = delay(i, 4 * q + 1) - o0, d2 = delay(i, 4 * q + 2) - o0,
+                  d3 = delay(i, 4 * q + 3) - o0;
+    size_t k = 0;
+    while (k < P.size() && !(P[k].d1 == d1 && P[k].d2 == d2 && P[k].d3 == d3)) ++k;
+    if (k == P.size()) {
+      if (k == 255) fail(GSP_EINVAL, "too many delay patterns in a quad");
+      P.push_back({d1, d2, d3, o0, o0});
+    } else {
+      P[k].lo = std::min(P[k].lo, o0);
+      P[k].hi = std::max(P[k].hi, o0);
+    }
+    pat_of[j] = (uint8_t)k;
+  }
+}
+
+// LDS dwords of staged copies one pass may hold (the two buffers share the
+// workgroup's LDS budget; kinds 2 and 3 keep no copy records in LDS)
+static int64_t quad_pass_dwords(const DedispShape &sh) {
+  const bool pc = sh.kind == 2 || sh.kind == 3;
+  const int rec_cap = pc ? INT32_MAX : std::min(64 * sh.waves, kQuadRecMax);
+  // two workgroups per CU up to 8 summing waves, one (all 160 KB) above
+  const int64_t budget = sh.waves > 8 ? kQuadLdsMax : kQuadLdsBudget;
+  return (budget / 4 - (pc ? 0 : 2 * 4 * (int64_t)rec_cap)) / 2;
+}
+
+void quad_split(const RowTables &rt, int32_t *c0, int32_t *c1) {
+  const DedispShape &sh = rt.shape;
+  if (rt.D != 1 || rt.nchan % 4) fail(GSP_EINVAL, "the byte-quad tile sums uint8 rows of whole channel quads");
+  const int nchan = rt.nchan, nq = nchan / 4, n_dm = rt.n_dm, MT = sh.trials_per_block();
+  const int T = 64 * sh.groups;
+  const int64_t dw_cap = quad_pass_dwords(sh);
+  const int32_t *d = rt.delays_host.data();
+  auto delay = [&](int i, int c) { return d[(int64_t)std::min(i, n_dm - 1) * nchan + c]; };
+  // a quad fits if its copies of every DM tile fit one pass (chunk count
+  // per copy as the table builder rounds it, every copy at the longest); it
+  // suits the tile if they also stay below kQuadSplitStaged of the dwords
+  // the tile's trials read from them
+  std::vector<uint8_t> fits(nq, 1), suits(nq, 1);
+  std::vector<QuadPat> P;
+  std::vector<uint8_t> pat_of(MT);
+  const double reads = (double)MT * T;
+  for (int i0 = 0; i0 < n_dm; i0 += MT)
+    for (int q = 0; q < nq; ++q) {
+      if (!fits[q]) continue;
+      quad_patterns(delay, i0, MT, q, P, pat_of.data());
+      int64_t cu = 0;
+      for (const QuadPat &p : P) cu = std::max<int64_t>(cu, (p.hi - p.lo + T + 3) / 4);
+      const int64_t staged = (int64_t)P.size() * cu * 4;
+      if (staged > dw_cap) fits[q] = suits[q] = 0;
+      if ((double)staged > kQuadSplitStaged * reads) suits[q] = 0;
+    }
+  if (std::all_of(fits.begin(), fits.end(), [](uint8_t f) { return f != 0; }))
+    fail(GSP_EINVAL, "every channel quad fits: the split tile does not apply");
+  int first_bad = nq, last_bad = -1;
+  for (int q = 0; q < nq; ++q)
+    if (!suits[q]) {
+      first_bad = std::min(first_bad, q);
+      last_bad = q;
+    }
+  // the 16-bit tile takes the shorter end run holding every quad that does
+  // not fit: [0, last_bad] or [first_bad, nq)
+  if (last_bad + 1 <= nq - first_bad) {
+    *c0 = 4 * (last_bad + 1);
+    *c1 = nchan;
+  } else {
+    *c0 = 0;
+    *c1 = 4 * first_bad;
+  }
+  if (*c1 <= *c0) fail(GSP_EINVAL, "no channel quad fits the byte-quad tile");
+}
+
+void quad_tables_host(const RowTables &rt, QuadHost &H, int64_t min_pitch) {
   const DedispShape &sh = rt.shape;
   if (rt.D != 1) fail(GSP_EINVAL, "the byte-quad tile sums uint8 rows only (D = 1)");
   if (rt.nchan % 4) fail(GSP_EINVAL, "the byte-quad tile needs a multiple of 4 channels");
@@ -443,19 +531,17 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   const int n_tiles = (n_dm + MT - 1) / MT;
   const int n_dm_pad = n_tiles * MT;
   const int T = 64 * sh.groups;
-  const bool pc = sh.kind == 2;  // staging waves: no register or record limit on a pass
+  const bool pc = sh.kind == 2 || sh.kind == 3;  // staging waves: no register or record limit on a pass
   const int threads = 64 * sh.waves;
   const int64_t chunk_cap = pc ? INT32_MAX : (int64_t)quad_chunks(sh.groups, sh.tpw) * threads;  // chunks per pass
   const int rec_cap = pc ? INT32_MAX : std::min(threads, kQuadRecMax);
-  // two buffers each of copies (and records): two workgroups per CU up to 8
-  // summing waves, one (all 160 KB) above
-  const int64_t budget = sh.waves > 8 ? kQuadLdsMax : kQuadLdsBudget;
-  const int64_t dw_cap = (budget / 4 - (pc ? 0 : 2 * 4 * (int64_t)rec_cap)) / 2;  // LDS dwords of copies per pass
+  const int64_t dw_cap = quad_pass_dwords(sh);  // LDS dwords of copies per pass
   const int64_t n_t = (rt.n_out + T - 1) / T;
   if ((n_t - 1) * T + rt.max_delay + dw_cap + 1024 >= (1LL << 30))
     fail(GSP_EINVAL, "row too long for the byte-quad tile's 32-bit offsets");
   // a pass's source offsets (from its first row) stay below 2^31
-  const int64_t pitch_ub = (std::max<int64_t>(rt.N, (n_t - 1) * T + rt.max_delay + dw_cap + 8) + 255) / 256 * 256;
+  const int64_t pitch_ub =
+      (std::max<int64_t>({rt.N, (n_t - 1) * T + rt.max_delay + dw_cap + 8, min_pitch}) + 255) / 256 * 256;
   const int64_t q_fit = ((1LL << 31) - 1 - pitch_ub) / (4 * pitch_ub);
   const int max_q = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)sh.chunk, kQuadPassMax, q_fit}));
   if (q_fit < 1) fail(GSP_EINVAL, "row too long for the byte-quad tile's 32-bit offsets");
@@ -472,32 +558,12 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   int rec_max = 1;
   double staged = 0;
 
-  struct Pat {
-    int32_t d1, d2, d3, lo, hi;
-  };
+  using Pat = QuadPat;
   std::vector<std::vector<Pat>> pats(nq);
   std::vector<std::vector<uint8_t>> pat_of(nq, std::vector<uint8_t>(MT));
   for (int tl = 0; tl < n_tiles; ++tl) {
     const int i0 = tl * MT;
-    for (int q = 0; q < nq; ++q) {
-      auto &P = pats[q];
-      P.clear();
-      for (int j = 0; j < MT; ++j) {
-        const int i = i0 + j;
-        const int32_t o0 = delay(i, 4 * q), d1 = delay(i, 4 * q + 1) - o0, d2 = delay(i, 4 * q + 2) - o0,
-                      d3 = delay(i, 4 * q + 3) - o0;
-        size_t k = 0;
-        while (k < P.size() && !(P[k].d1 == d1 && P[k].d2 == d2 && P[k].d3 == d3)) ++k;
-        if (k == P.size()) {
-          if (k == 255) fail(GSP_EINVAL, "too many delay patterns in a quad");
-          P.push_back({d1, d2, d3, o0, o0});
-        } else {
-          P[k].lo = std::min(P[k].lo, o0);
-          P[k].hi = std::max(P[k].hi, o0);
-        }
-        pat_of[q][j] = (uint8_t)k;
-      }
-    }
+    for (int q = 0; q < nq; ++q) quad_patterns(delay, i0, MT, q, pats[q], pat_of[q].data());
     // passes: consecutive quads while their copies (all at the pass's
     // largest chunk count) fit the LDS budget, the staging registers and
     // the record area
@@ -565,7 +631,7 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   // staged pitch: a chunk reads 4 bytes from sample t0 + s + 4 c with
   // s <= max_delay and c below the pass's chunk count
   const int64_t far = (n_t - 1) * T + rt.max_delay + 4 * max_cu + 8;
-  H.pitch = (std::max(far, rt.N) + 255) / 256 * 256;
+  H.pitch = (std::max({far, rt.N, min_pitch}) + 255) / 256 * 256;
   if (H.pitch > pitch_ub) fail(GSP_EINVAL, "byte-quad pitch bound");
   H.copies.resize(cp_start.size());
   for (size_t k = 0; k < cp_q.size(); ++k)
@@ -577,12 +643,53 @@ void quad_tables_host(const RowTables &rt, QuadHost &H) {
   H.max_q = max_q;
 }
 
+// Columns [c0, c1) of a row's delay table
+static std::vector<int32_t> delay_columns(const RowTables &rt, int32_t c0, int32_t c1) {
+  std::vector<int32_t> out((size_t)rt.n_dm * (c1 - c0));
+  for (int32_t i = 0; i < rt.n_dm; ++i)
+    std::copy(rt.delays_host.begin() + (int64_t)i * rt.nchan + c0, rt.delays_host.begin() + (int64_t)i * rt.nchan + c1,
+              out.begin() + (int64_t)i * (c1 - c0));
+  return out;
+}
+
 void build_quad_tables(gsp_ctx *ctx, RowTables &rt) {
   QuadHost H;
-  quad_tables_host(rt, H);
+  if (rt.shape.kind == 3) {
+    // split row: the byte-quad tile over [c0, c1), the 16-bit tile (default
+    // shape) over the channels at the other end; one staging of the whole
+    // row at a pitch both accept
+    int32_t c0 = 0, c1 = 0;
+    quad_split(rt, &c0, &c1);
+    const int32_t l0 = c0 > 0 ? 0 : c1, l1 = c0 > 0 ? c0 : rt.nchan;
+    auto low = std::make_unique<RowTables>();
+    low->delays_host = delay_columns(rt, l0, l1);
+    DedispShape ps;  // the 16-bit tile's default: (4, 4, 8, 32)
+    ps.groups = 4;
+    ps.tpw = 4;
+    ps.waves = 8;
+    ps.chunk = 32;
+    ps.kind = 0;
+    build_tables_from_delays(ctx, rt.n_dm, l1 - l0, rt.D, rt.N, rt.n_out, rt.max_delay, ps, *low);
+    low->y_ch0 = l0;
+    RowTables sub;  // the byte-quad part as a row of its own
+    sub.n_dm = rt.n_dm;
+    sub.D = rt.D;
+    sub.nchan = c1 - c0;
+    sub.N = rt.N;
+    sub.n_out = rt.n_out;
+    sub.max_delay = rt.max_delay;
+    sub.shape = rt.shape;
+    sub.delays_host = delay_columns(rt, c0, c1);
+    quad_tables_host(sub, H, staged_pitch(*low));
+    low->pitch_override = H.pitch;
+    rt.y_ch0 = c0;
+    rt.low = std::move(low);
+  } else {
+    quad_tables_host(rt, H);
+  }
   rt.q_pitch = H.pitch;
   rt.data_dw = (int32_t)H.lds_dw;
-  rt.q_rec_dw = rt.shape.kind == 2 ? 0 : 4 * H.rec_max;
+  rt.q_rec_dw = (rt.shape.kind == 2 || rt.shape.kind == 3) ? 0 : 4 * H.rec_max;
   rt.lds_bytes = 2 * (H.lds_dw + rt.q_rec_dw) * 4;
   rt.q_staged_dw = H.staged;
   rt.max_chunk = H.max_q;
@@ -620,8 +727,9 @@ void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hip
   const DedispShape &sh = rt.shape;
   QuadArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.Y = ctx->staged.as<uint8_t>();
+  a.Y = ctx->staged.as<uint8_t>() + (int64_t)rt.y_ch0 * rt.q_pitch;
   a.pitch = rt.q_pitch;
+  a.accumulate = sh.kind == 3 ? 1 : 0;  // after the 16-bit tile's part of the row
   a.addr = rt.addr.as<uint32_t>();
   a.tile_pass = rt.q_tile_pass.as<int32_t>();
   a.passes = rt.q_passes.as<int4>();
@@ -639,8 +747,9 @@ void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hip
   const int64_t n_t = (rt.n_out + T - 1) / T;
   if ((int64_t)a.n_dm_tiles * n_t >= (1LL << 31)) fail(GSP_EOVERFLOW, "too many dedispersion tiles");
   a.n_t_tiles = (int32_t)n_t;
-  ProfScope prof(ctx, "dedisperse_quad", st, (double)rt.n_dm * (double)rt.n_out * (double)rt.nchan);
-  if (sh.kind == 2) {
+  const int32_t qch = rt.low ? rt.nchan - rt.low->nchan : rt.nchan;  // channels of this tile
+  ProfScope prof(ctx, "dedisperse_quad", st, (double)rt.n_dm * (double)rt.n_out * (double)qch);
+  if (sh.kind == 2 || sh.kind == 3) {
     switch (sh.groups * 16 + sh.tpw) {
       case 8 * 16 + 4: launch_qpc<8, 4>(a, sh.waves, rt.lds_bytes, st); break;
       case 4 * 16 + 8: launch_qpc<4, 8>(a, sh.waves, rt.lds_bytes, st); break;

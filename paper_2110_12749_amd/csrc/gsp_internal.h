@@ -42,7 +42,9 @@ struct DedispShape {
   int groups = 8;    // dword groups per lane (samples per block = 128 * groups)
   int chunk = 32;    // channels staged per pass (kind 1: channel quads per pass)
   int kind = 0;      // 0: 16-bit pair tile (any row); 1: byte-quad tile (D = 1, nchan % 4 == 0);
-                     // 2: byte-quad tile with 4 staging waves besides `waves` summing waves
+                     // 2: byte-quad tile with 4 staging waves besides `waves` summing waves;
+                     // 3: kind 2 over the channels whose copies fit, the 16-bit tile (default
+                     //    shape) over a run of channels at one end of the band whose copies do not
   int trials_per_block() const { return tpw * waves; }
   // kind 0: a lane sums `groups` dwords of two samples; kinds 1, 2: `groups` dwords of one sample
   int samples_per_block() const { return (kind != 0 ? 64 : 128) * groups; }
@@ -69,6 +71,9 @@ struct RowTables {
   DevBuf q_passes;           // int4 per pass {first quad, first copy, chunks per copy, magic} + a sentinel per tile
   DevBuf q_copies;           // int4 per staged copy: source byte offset of each of its 4 channels
   int64_t q_pitch = 0;       // staged pitch the quad tile needs
+  int32_t y_ch0 = 0;         // first staged channel row the tables read (the row's own channels from here)
+  int64_t pitch_override = 0;  // staged pitch shared with the other part of a split row (0: own)
+  std::unique_ptr<RowTables> low;  // kind 3: the 16-bit tile's part of the row
   int32_t q_rec_dw = 0;      // LDS dwords of one buffer of copy records (data_dw: of copies)
   double q_staged_dw = 0;    // LDS dwords staged per time tile, summed over DM tiles (profile)
 };
@@ -228,7 +233,13 @@ struct QuadHost {                  // the byte-quad tile's tables on the host
   double staged = 0;               // LDS dwords staged per time tile, all DM tiles
   int max_q = 0;
 };
-void quad_tables_host(const RowTables &rt, QuadHost &H);
+void quad_tables_host(const RowTables &rt, QuadHost &H, int64_t min_pitch = 0);
+// kind 3: the channel range [*c0, *c1) the byte-quad tile takes (a multiple of
+// 4 channels whose copies fit one pass each); the rest of the band, at one
+// end of it, goes to the 16-bit tile.  Fails (GSP_EINVAL) where every quad
+// fits (kind 2 applies) or where the quads that do not fit are not all at
+// one end of the band.
+void quad_split(const RowTables &rt, int32_t *c0, int32_t *c1);
 void build_quad_tables(gsp_ctx *ctx, RowTables &rt);
 void launch_dedisp_quad(gsp_ctx *ctx, const RowTables &rt, int32_t *out_row, hipStream_t st);
 

@@ -134,3 +134,81 @@ def test_quad_default_on_few_channels(dev, nchan, nsamp, tsamp, seg, kind):
     finally:
         torch.cuda.synchronize()
         ctx.close()
+
+
+@pytest.fixture(scope="module")
+def split_case(dev):
+    """A wide band (256 channels over 270-1620 MHz): on the D = 1 row the
+    lowest quads' delay copies do not fit the byte-quad tile, so the row's
+    band is split between the two tiles; a D = 2 row keeps the 16-bit tile."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    w = synth.small(nchan=256, nsamp=40000, segments=[(0.0, 0.1, 200, 1), (20.0, 0.3, 40, 2)], f_lo=270.0,
+                    f_hi=1620.0, n_pulses=2, seed_offset=33)
+    X = w.generate()
+    ref = oracle.dedisperse(X, w.freqs, w.tsamp, w.segments)
+    fb = torch.from_numpy(X).to("cuda")
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    ctx = gsp.Context(0)
+    yield gsp, ctx, w, fb, desc, ref, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _check_rows(gsp, ctx, w, fb, desc, ref, torch):
+    dmt = ctx.dedisperse(fb, w.freqs, desc, out=torch.full((desc.total,), -1, dtype=torch.int32, device="cuda"))
+    views = gsp.segment_views(desc, dmt)
+    for s in range(desc.n_seg):
+        got = views[s].cpu().numpy()
+        bad = np.argwhere(got != ref[s])
+        assert len(bad) == 0, f"row {s}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+
+
+def test_split_is_default_on_a_wide_band(split_case):
+    gsp, ctx, w, fb, desc, ref, torch = split_case
+    say(f"[case] split default, shapes {ctx.row_shape(w.freqs, desc, 0)} {ctx.row_shape(w.freqs, desc, 1)}")
+    assert ctx.row_shape(w.freqs, desc, 0)[4] == 3
+    assert ctx.row_shape(w.freqs, desc, 1)[4] == 0
+    _check_rows(gsp, ctx, w, fb, desc, ref, torch)
+
+
+@pytest.mark.parametrize("descending", [False, True])
+def test_split_either_band_order(dev, descending):
+    """Channels in descending frequency: the quads that do not fit are at the
+    high-index end, and the 16-bit tile takes that end."""
+    import torch
+    from paper_2110_12749_amd import gsp
+    w = synth.small(nchan=128, nsamp=30000, segments=[(0.0, 0.2, 70, 1)], f_lo=270.0, f_hi=1620.0, n_pulses=1,
+                    seed_offset=34)
+    X, freqs = w.generate(), w.freqs
+    if descending:  # the same data with the channel axis reversed
+        X, freqs = np.ascontiguousarray(X[:, ::-1]), freqs[::-1].copy()
+    ref = oracle.dedisperse(X, freqs, w.tsamp, w.segments)
+    desc = gsp.plan_shape(w.nsamp, freqs, w.tsamp, w.segments)
+    ctx = gsp.Context(0)
+    try:
+        say(f"[case] split, descending={descending}: shape {ctx.row_shape(freqs, desc, 0)}")
+        assert ctx.row_shape(freqs, desc, 0)[4] == 3
+        dmt = ctx.dedisperse(torch.from_numpy(X).to("cuda"), freqs, desc,
+                             out=torch.full((desc.total,), -1, dtype=torch.int32, device="cuda"))
+        got = gsp.segment_views(desc, dmt)[0].cpu().numpy()
+        bad = np.argwhere(got != ref[0])
+        assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:5].tolist()}"
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+
+def test_split_rejected_where_every_quad_fits(quad_case):
+    gsp, ctx, w, fb, desc, ref, torch = quad_case
+    with pytest.raises(gsp.GspError):
+        ctx.set_row_shape(w.freqs, desc, 0, 4, 8, 8, 64, 3)
+
+
+def test_split_tuned_then_parity(split_case):
+    """The autotuner times the split tile against the others on this row
+    (whichever wins, the sums stay exact)."""
+    gsp, ctx, w, fb, desc, ref, torch = split_case
+    shapes = ctx.autotune(fb, w.freqs, desc, n_reps=1)
+    say(f"  tuned {shapes}")
+    _check_rows(gsp, ctx, w, fb, desc, ref, torch)
