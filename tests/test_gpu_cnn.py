@@ -343,6 +343,19 @@ def test_cutouts_large_batch(env, case):
     cutout_case(env, w, extra, batch=300, check=list(range(first)) + list(range(first, 300, 9)))
 
 
+def test_cutouts_on_a_split_row(env):
+    """A wide band (256 channels over 270-1620 MHz) whose D = 1 row is split
+    between the byte-quad and the 16-bit tiles: the cutouts take the row's
+    delays and DM-time series like any other row's."""
+    gsp, ctx, torch = env
+    segs = [(0.0, 0.1, 200, 1), (20.0, 0.3, 40, 2)]
+    w = synth.small(nchan=256, nsamp=40000, segments=segs, f_lo=270.0, f_hi=1620.0, n_pulses=2, seed_offset=35,
+                    widths=[1, 2, 4, 8, 16, 32])
+    desc = gsp.plan_shape(w.nsamp, w.freqs, w.tsamp, w.segments)
+    assert ctx.row_shape(w.freqs, desc, 0)[4] == 3
+    cutout_case(env, w, [(0, 0, 0, 1), (0, 199, 20000, 32), (1, 39, 100, 8), (0, 120, 5, 16)])
+
+
 def test_cutouts_invalid_candidates_give_zero_images(env):
     gsp, ctx, torch = env
     w = synth.tiny()
