@@ -94,10 +94,11 @@ RowTables &row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freq
         build_row_tables(ctx, desc, freqs, s, split, *rt);
       } catch (const Error &e2) {
         if (e2.status != GSP_EINVAL) throw;
-        DedispShape pair = want;
+        DedispShape pair;  // the 16-bit tile's default (4, 4, 8, 32)
         pair.kind = 0;
         pair.groups = 4;
         pair.tpw = 4;
+        pair.waves = 8;
         pair.chunk = 32;
         rt = std::make_unique<RowTables>();
         rt->delays_host = std::move(delays);

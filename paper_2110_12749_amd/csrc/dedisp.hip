@@ -170,10 +170,11 @@ DedispShape default_shape(int32_t D, int32_t nchan) {
   s.waves = 8;
   s.groups = 4;
   s.chunk = 32;
-  if (D == 1 && nchan % 4 == 0) {  // byte-quad tile with staging waves
+  if (D == 1 && nchan % 4 == 0) {  // byte-quad tile with staging waves: 12 summing waves
     s.kind = 2;
     s.groups = 4;
     s.tpw = 8;
+    s.waves = 12;
     s.chunk = 64;
   }
   return s;
@@ -222,6 +223,7 @@ int64_t staged_pitch(const RowTables &rt) {
 
 void build_row_tables(gsp_ctx *ctx, const gsp_dmt_desc *desc, const double *freqs, int32_t s,
                       const DedispShape &shape, RowTables &rt, int units_per_thread) {
+  if (!shape_supported(shape)) fail(GSP_EINVAL, "unsupported dedispersion shape");
   const gsp_segment &g = desc->seg[s];
   if (rt.delays_host.empty()) {
     rt.delays_host.resize((size_t)g.n_dm * desc->nchan);

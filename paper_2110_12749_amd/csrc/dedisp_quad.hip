@@ -470,8 +470,10 @@ static void quad_patterns(DELAY delay, int i0, int MT, int q, std::vector<QuadPa
 static int64_t quad_pass_dwords(const DedispShape &sh) {
   const bool pc = sh.kind == 2 || sh.kind == 3;
   const int rec_cap = pc ? INT32_MAX : std::min(64 * sh.waves, kQuadRecMax);
-  // two workgroups per CU up to 8 summing waves, one (all 160 KB) above
-  const int64_t budget = sh.waves > 8 ? kQuadLdsMax : kQuadLdsBudget;
+  // two workgroups per CU: up to 8 waves in kind 1, and in kinds 2 and 3 up
+  // to 12 summing waves (with the 4 staging waves two 16-wave workgroups of
+  // 60 VGPRs fill a CU, 4 waves per SIMD each); kind 1 above 8: one (160 KB)
+  const int64_t budget = (pc || sh.waves <= 8) ? kQuadLdsBudget : kQuadLdsMax;
   return (budget / 4 - (pc ? 0 : 2 * 4 * (int64_t)rec_cap)) / 2;
 }
 

@@ -31,7 +31,7 @@ DedispShape mk(int groups, int tpw, int waves, int chunk, int kind = 0) {
 const DedispShape kCandidates[] = {
     mk(4, 4, 8, 16), mk(4, 4, 8, 32), mk(4, 8, 4, 16), mk(4, 8, 4, 32), mk(2, 8, 8, 16),
     mk(2, 8, 4, 32), mk(4, 4, 4, 16), mk(8, 4, 8, 16),
-    mk(4, 8, 8, 64, 2), mk(4, 8, 12, 64, 2), mk(8, 4, 8, 64, 2), mk(4, 8, 4, 64, 2), mk(4, 8, 8, 64, 3),
+    mk(4, 8, 8, 64, 2), mk(4, 8, 12, 64, 2), mk(8, 4, 8, 64, 2), mk(4, 8, 4, 64, 2), mk(4, 8, 8, 64, 3), mk(4, 8, 12, 64, 3),
     mk(4, 8, 8, 64, 1), mk(8, 4, 16, 64, 1),
 };
 
