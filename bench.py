@@ -306,7 +306,8 @@ SWEEP_SHAPES = [(4, 4, 8, 32), (4, 4, 8, 16), (4, 4, 8, 8), (4, 4, 4, 32), (4, 8
                 (8, 4, 8, 64, 1), (8, 4, 16, 64, 1), (8, 2, 16, 64, 1), (4, 8, 8, 64, 1), (16, 2, 16, 64, 1),
                 (4, 4, 16, 64, 1), (4, 8, 16, 64, 1), (4, 8, 4, 64, 1),
                 # byte-quad tile with 4 staging waves besides the summing ones
-                (4, 8, 8, 64, 2), (8, 4, 8, 64, 2), (4, 8, 12, 64, 2), (8, 4, 12, 64, 2), (4, 8, 4, 64, 2),
+                (4, 8, 12, 64, 2), (4, 8, 8, 64, 2), (4, 8, 10, 64, 2), (8, 4, 8, 64, 2), (8, 4, 12, 64, 2),
+                (4, 8, 4, 64, 2),
                 # split rows: kind 2 over the channels whose copies fit, the 16-bit tile over the rest
                 (4, 8, 8, 64, 3), (4, 8, 12, 64, 3), (8, 4, 8, 64, 3),
                 (8, 4, 4, 64, 2)]
