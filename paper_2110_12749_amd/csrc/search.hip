@@ -122,11 +122,14 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const SeriesTable *__re
 // One wave owns one item: a trial and a segment [s0, s1) of its box ends.  It
 // walks the samples from lo = max(first valid sample, s0 - (w_max - 1)) in
 // blocks of 8 x 64: each lane holds one sample per 64-sample step, a wave-wide
-// int64 scan (DPP) plus the running carry gives the exact prefix sums P, and
-// these go into a per-wave LDS ring that keeps the last RING of them.  A box
-// (e, w) sums to P(e) - P(e - w).  Per width an integer prefilter flags the
-// box ends whose sum can reach the threshold; only those get the exact double
-// SNR.  Runs of flagged ends are followed across steps and blocks inside the
+// scan (DPP) plus the running carry gives the exact prefix sums C of the
+// samples less the trial's integer mean c, and these go into a per-wave LDS
+// ring that keeps the last RING of them.  A box (e, w) sums to
+// C(e) - C(e - w) + w c.  Per width an integer prefilter flags the box ends
+// whose sum can reach the threshold (in 32 bits, on the ring's low halves,
+// wherever no sample within a box's reach lies 2^31 / w_max or more from c,
+// so that every box's C difference fits; in 64 bits elsewhere); only those
+// get the exact double SNR.  Runs of flagged ends are followed across steps and blocks inside the
 // wave and written as fragments (one atomic each).  Waves never wait for each
 // other: there is no workgroup barrier after the widths are loaded.
 static constexpr int kSearchThreads = 256;
@@ -194,7 +197,14 @@ __device__ __forceinline__ int64_t lane63(int64_t v) { return readlane_i64(v, 63
 // lane, and the open run.
 template <int RING>
 struct SearchWaveLds {
-  int64_t ring[RING];
+  int32_t ring_lo[RING], ring_hi[RING];  // the centred prefix sums, low and high halves
+  __device__ int64_t get(int j) const {
+    return (int64_t)(((uint64_t)(uint32_t)ring_hi[j] << 32) | (uint32_t)ring_lo[j]);
+  }
+  __device__ void put(int j, int64_t v) {
+    ring_lo[j] = (int32_t)(uint32_t)v;
+    ring_hi[j] = (int32_t)(uint32_t)((uint64_t)v >> 32);
+  }
   double sb[64];
   int32_t sk[64];
   int64_t o_first, o_peak;
@@ -245,15 +255,25 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
     // its double rounding), so every box end the exact test flags passes
     // (lane k holds width k and its bound; the loops below read them with
     // readlane, so they cost no LDS round trip)
+    // The bound is kept against the centred sums: C difference >= lim - w c,
+    // in 64 bits and, clamped, in 32 (a clamp only lets more ends through).
     int lane_w = 0;
     int64_t lane_lim = INT64_MAX;
+    int32_t lane_l32 = INT32_MAX;
     if (lane < nw) {
       lane_w = wsh[lane];
       const double wd = (double)lane_w;
       const double bound = wd * mu + thr * sigma * sqrt(wd);
       lane_lim = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
+      if (lane_lim != INT64_MIN && lane_lim != INT64_MAX) lane_lim -= cmean * (int64_t)lane_w;
+      lane_l32 = (int32_t)max((int64_t)INT32_MIN, min((int64_t)INT32_MAX, lane_lim));
     }
-    if (lane == 0) W.ring[0] = 0;  // P(lo - 1)
+    // samples this far from c or farther make the 32-bit prefilter unsafe for
+    // the boxes that reach them (w_max of them sum to less than 2^31 in size)
+    const int64_t big = (int64_t)(0x7FFFFFFF / (uint32_t)a.wmax);
+    const int64_t reach_blocks = (a.wmax - 1 + kSearchBlock - 1) / kSearchBlock;
+    int64_t last_big = -(reach_blocks + 1);  // the last block holding such a sample
+    if (lane == 0) W.put(0, 0);  // C(lo - 1)
     __builtin_amdgcn_wave_barrier();
 
     bool open = false;
@@ -293,9 +313,10 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int it = 0; it < 8; ++it) vn[it] = x[min(eb + kSearchBlock + 64 * it + lane, s1 - 1)];
       }
-      // ---- exact prefix sums into the ring ----
+      // ---- exact centred prefix sums into the ring ----
       const int r0 = (int)(eb - lo + 1);
-      int64_t P[8];
+      int64_t P[8];  // C at the lane's box end + 1
+      bool blk_big = false;
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
         const int64_t e = eb + 64 * it + lane;
@@ -304,12 +325,14 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
         // (positions past the segment count as c, i.e. add nothing)
         const int64_t y = e < s1 ? (int64_t)v[it] - cmean : 0;
         if (__ballot(y <= -(int64_t)(1 << 25) || y >= (int64_t)(1 << 25)) == 0ull)
-          P[it] = carry + (int64_t)wave_scan_i32((int32_t)y) + cmean * (int64_t)(lane + 1);
+          P[it] = carry + (int64_t)wave_scan_i32((int32_t)y);
         else
-          P[it] = carry + wave_scan_i64(y) + cmean * (int64_t)(lane + 1);
+          P[it] = carry + wave_scan_i64(y);
+        blk_big |= __ballot(y <= -big || y >= big) != 0ull;
         carry = lane63(P[it]);
-        W.ring[(r0 + 64 * it + lane) & (RING - 1)] = P[it];
+        W.put((r0 + 64 * it + lane) & (RING - 1), P[it]);
       }
+      if (blk_big) last_big = blk;
       __builtin_amdgcn_wave_barrier();
       if (eb + kSearchBlock - 1 < s0) continue;  // look-back block: sums only
 
@@ -318,14 +341,30 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
       uint64_t mk[8];
 #pragma unroll
       for (int it = 0; it < 8; ++it) mk[it] = 0;
-      if (full) {
+      if (full && blk - last_big > reach_blocks) {
+        // every box of the block sums to less than 2^31 in size about w c:
+        // the C differences are exact in 32 bits (the ring's low halves)
+        uint32_t p32[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) p32[it] = (uint32_t)P[it];
+        for (int k = 0; k < nw; ++k) {
+          const int w = __builtin_amdgcn_readlane(lane_w, k);
+          const int32_t L = __builtin_amdgcn_readlane(lane_l32, k);
+          const int bw = r0 + lane - w;
+          uint32_t qv[8];
+#pragma unroll
+          for (int it = 0; it < 8; ++it) qv[it] = (uint32_t)W.ring_lo[(bw + 64 * it) & (RING - 1)];
+#pragma unroll
+          for (int it = 0; it < 8; ++it) mk[it] |= __ballot((int32_t)(p32[it] - qv[it]) >= L);
+        }
+      } else if (full) {
         for (int k = 0; k < nw; ++k) {
           const int w = __builtin_amdgcn_readlane(lane_w, k);
           const int64_t L = readlane_i64(lane_lim, k);
           const int bw = r0 + lane - w;
           int64_t qv[8];
 #pragma unroll
-          for (int it = 0; it < 8; ++it) qv[it] = W.ring[(bw + 64 * it) & (RING - 1)];
+          for (int it = 0; it < 8; ++it) qv[it] = W.get((bw + 64 * it) & (RING - 1));
 #pragma unroll
           for (int it = 0; it < 8; ++it) mk[it] |= __ballot(P[it] - qv[it] >= L);
         }
@@ -336,7 +375,7 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
           const int bw = r0 + lane - w;
           int64_t qv[8];
 #pragma unroll
-          for (int it = 0; it < 8; ++it) qv[it] = W.ring[(bw + 64 * it) & (RING - 1)];
+          for (int it = 0; it < 8; ++it) qv[it] = W.get((bw + 64 * it) & (RING - 1));
 #pragma unroll
           for (int it = 0; it < 8; ++it)
             mk[it] |= __ballot((P[it] - qv[it] >= L) & ((int64_t)w <= eb + 64 * it + lane + look + 1));
@@ -361,11 +400,11 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
         int kb = 0;
         if (maybe) {
           const int re = (int)(e - lo + 1);
-          const int64_t q1 = W.ring[re & (RING - 1)];
+          const int64_t q1 = W.get(re & (RING - 1));
           for (int k = 0; k < nw; ++k) {
             const int w = wsh[k];
             if ((int64_t)w > e + look + 1) break;  // box would start before the first sample
-            const double sum = (double)(q1 - W.ring[(re - w) & (RING - 1)]);
+            const double sum = (double)(q1 - W.get((re - w) & (RING - 1)) + cmean * (int64_t)w);
             const double snr = (sum - (double)w * mu) / (sigma * sqrt((double)w));
             if (kb == 0 || snr > bs) {
               bs = snr;
