@@ -260,9 +260,12 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
     int lane_w = 0;
     int64_t lane_lim = INT64_MAX;
     int32_t lane_l32 = INT32_MAX;
+    double lane_wmu = 0.0, lane_den = 1.0;  // w mu and sigma sqrt(w), as the exact SNR takes them
     if (lane < nw) {
       lane_w = wsh[lane];
       const double wd = (double)lane_w;
+      lane_wmu = wd * mu;
+      lane_den = sigma * sqrt(wd);
       const double bound = wd * mu + thr * sigma * sqrt(wd);
       lane_lim = bound < -4.0e18 ? INT64_MIN : (bound > 4.0e18 ? INT64_MAX : (int64_t)floor(bound) - 2);
       if (lane_lim != INT64_MIN && lane_lim != INT64_MAX) lane_lim -= cmean * (int64_t)lane_w;
@@ -401,12 +404,21 @@ __global__ __launch_bounds__(kSearchThreads) __attribute__((amdgpu_waves_per_eu(
         if (maybe) {
           const int re = (int)(e - lo + 1);
           const int64_t q1 = W.get(re & (RING - 1));
+          // only widths whose integer sum passes the prefilter bound can
+          // reach the threshold; when one does, the best width is among them
+          // (a width below its bound has an SNR below the threshold), so the
+          // others are skipped, for the whole wave when none of its lanes pass
           for (int k = 0; k < nw; ++k) {
-            const int w = wsh[k];
+            const int w = __builtin_amdgcn_readlane(lane_w, k);
             if ((int64_t)w > e + look + 1) break;  // box would start before the first sample
-            const double sum = (double)(q1 - W.get((re - w) & (RING - 1)) + cmean * (int64_t)w);
-            const double snr = (sum - (double)w * mu) / (sigma * sqrt((double)w));
-            if (kb == 0 || snr > bs) {
+            const int64_t d = q1 - W.get((re - w) & (RING - 1));  // C difference
+            const bool pass = d >= readlane_i64(lane_lim, k);
+            if (__ballot(pass) == 0ull) continue;
+            const double sum = (double)(d + cmean * (int64_t)w);
+            const double wmu = __builtin_bit_cast(double, readlane_i64(__builtin_bit_cast(int64_t, lane_wmu), k));
+            const double den = __builtin_bit_cast(double, readlane_i64(__builtin_bit_cast(int64_t, lane_den), k));
+            const double snr = (sum - wmu) / den;
+            if (pass && (kb == 0 || snr > bs)) {
               bs = snr;
               kb = k + 1;
             }
