@@ -300,10 +300,25 @@ int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc
     std::vector<Frag> fr(count);
     if (count)
       check_hip(hipMemcpy(fr.data(), ctx->frags.ptr, count * sizeof(Frag), hipMemcpyDeviceToHost), "copy fragments");
-    // join fragments split at tile edges
-    std::sort(fr.begin(), fr.end(), [](const Frag &a, const Frag &b) {
-      return a.trial != b.trial ? a.trial < b.trial : a.t_first < b.t_first;
-    });
+    // join fragments split at tile edges: order them by (trial, first box
+    // end) with a counting pass over the trials and a sort of each trial's
+    // few fragments (a trial's runs are disjoint, so the order is unique)
+    {
+      std::vector<int64_t> start((size_t)desc->n_trials + 1, 0);
+      for (const Frag &f : fr) {
+        if (f.trial < 0 || f.trial >= desc->n_trials) fail(GSP_EDEVICE, "search fragment of an unknown trial");
+        ++start[(size_t)f.trial + 1];
+      }
+      for (int32_t g = 0; g < desc->n_trials; ++g) start[(size_t)g + 1] += start[(size_t)g];
+      std::vector<Frag> by_trial(fr.size());
+      std::vector<int64_t> fill(start.begin(), start.end() - 1);
+      for (const Frag &f : fr) by_trial[(size_t)fill[(size_t)f.trial]++] = f;
+      for (int32_t g = 0; g < desc->n_trials; ++g)
+        if (start[(size_t)g + 1] - start[(size_t)g] > 1)
+          std::sort(by_trial.begin() + start[(size_t)g], by_trial.begin() + start[(size_t)g + 1],
+                    [](const Frag &a, const Frag &b) { return a.t_first < b.t_first; });
+      fr.swap(by_trial);
+    }
     std::vector<Frag> runs;
     runs.reserve(fr.size());
     for (const Frag &f : fr) {
@@ -340,12 +355,17 @@ int gsp_single_pulse_search(gsp_ctx *ctx, const int32_t *dmt, const gsp_dmt_desc
       c.snr = (float)f.snr;
       c.time_s = ((double)c.t_peak + 0.5 * (double)c.width) * (double)desc->seg[s].downsamp * desc->tsamp;
     }
-    std::sort(out.begin(), out.end(), [](const gsp_candidate &a, const gsp_candidate &b) {
-      if (a.seg != b.seg) return a.seg < b.seg;
-      if (a.dm_index != b.dm_index) return a.dm_index < b.dm_index;
-      if (a.t_peak != b.t_peak) return a.t_peak < b.t_peak;
-      return a.t_first < b.t_first;
-    });
+    // (seg, dm_index) is the trial order the runs already follow: sort each
+    // trial's candidates by (t_peak, t_first)
+    for (size_t b = 0; b < out.size();) {
+      size_t e = b + 1;
+      while (e < out.size() && out[e].seg == out[b].seg && out[e].dm_index == out[b].dm_index) ++e;
+      if (e - b > 1)
+        std::sort(out.begin() + (int64_t)b, out.begin() + (int64_t)e, [](const gsp_candidate &x, const gsp_candidate &y) {
+          return x.t_peak != y.t_peak ? x.t_peak < y.t_peak : x.t_first < y.t_first;
+        });
+      b = e;
+    }
     *n_found = (int64_t)out.size();
     const int64_t nw = std::min<int64_t>(capacity, (int64_t)out.size());
     if (nw > 0) std::memcpy(cands, out.data(), (size_t)nw * sizeof(gsp_candidate));
