@@ -386,11 +386,27 @@ int gsp_group_candidates(const gsp_candidate *c, int64_t n, int64_t *rep, int64_
     std::vector<int64_t> parent(n), order(n);
     std::iota(parent.begin(), parent.end(), 0);
     std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-      if (c[a].seg != c[b].seg) return c[a].seg < c[b].seg;
-      if (c[a].dm_index != c[b].dm_index) return c[a].dm_index < c[b].dm_index;
-      return c[a].t_first < c[b].t_first;
-    });
+    // a search's output already runs in (seg, dm_index) order: then only each
+    // trial's few candidates need ordering by t_first
+    bool trial_order = true;
+    for (int64_t k = 1; k < n && trial_order; ++k)
+      trial_order = c[k - 1].seg < c[k].seg || (c[k - 1].seg == c[k].seg && c[k - 1].dm_index <= c[k].dm_index);
+    if (trial_order) {
+      for (int64_t b = 0; b < n;) {
+        int64_t e = b + 1;
+        while (e < n && c[e].seg == c[b].seg && c[e].dm_index == c[b].dm_index) ++e;
+        if (e - b > 1)
+          std::sort(order.begin() + b, order.begin() + e,
+                    [&](int64_t x, int64_t y) { return c[x].t_first < c[y].t_first; });
+        b = e;
+      }
+    } else {
+      std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        if (c[a].seg != c[b].seg) return c[a].seg < c[b].seg;
+        if (c[a].dm_index != c[b].dm_index) return c[a].dm_index < c[b].dm_index;
+        return c[a].t_first < c[b].t_first;
+      });
+    }
     auto find = [&](int64_t v) {
       while (parent[v] != v) v = parent[v] = parent[parent[v]];
       return v;

@@ -110,10 +110,15 @@ def _rand_cands(rng, n, n_trials=12, T=400):
     return c[np.array(sorted(keep))]
 
 
-def test_grouping_matches_oracle(gsp):
+@pytest.mark.parametrize("search_order", [False, True])
+def test_grouping_matches_oracle(gsp, search_order):
+    """Any candidate order, and the search's own (seg, dm_index, t_peak)
+    order, whose trials the grouping then orders one by one."""
     rng = np.random.default_rng(0)
     for trial in range(30):
         c = _rand_cands(rng, 200)
+        if search_order:
+            c = c[np.lexsort((c["t_first"], c["t_peak"], c["dm_index"], c["seg"]))]
         rep, ng = gsp.group_candidates(c)
         for s in (0, 1):
             idx = np.nonzero(c["seg"] == s)[0]
