@@ -508,7 +508,11 @@ int gsp_profile_read(gsp_ctx *ctx, gsp_kernel_stat *out, int32_t cap, int32_t *n
  * trial or box end lies outside the plan gets two zero images.  out_dev: device
  * bf16 (uint16) [n][2][64][64].  Asynchronous on `stream`.  Trial means are
  * computed only for the trials of images whose first bin starts before the
- * data (a pass over those rows alone).  The context keeps
+ * data (a pass over those rows alone).  Batches of 256 or more candidates
+ * read a channel-major copy of fb_dev: the one the last gsp_dedisperse on
+ * this context left staged when it wrote dmt_dev from fb_dev and ended with
+ * a row without downsampling (it orders such rows last), else one made here
+ * in the context's staging buffer.  The context keeps
  * a device buffer of 16 KB per candidate for the frequency-time band sums
  * (grown, with a device synchronisation, when a call has more candidates
  * than any before it). */

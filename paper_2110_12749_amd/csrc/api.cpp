@@ -234,11 +234,16 @@ int gsp_dedisperse(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const g
     if (fref_of(freqs, desc->nchan) != desc->fref_mhz)
       fail(GSP_EINVAL, "frequencies differ from those the plan was shaped with");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int32_t s = 0; s < desc->n_seg; ++s) {
-      RowTables &rt = row_tables(ctx, desc, freqs, s);
-      stage_row(ctx, fb, desc, rt, st);
-      launch_dedisp(ctx, rt, dmt + desc->offset[s], st);
-    }
+    // rows without downsampling last: their staged rows are the channel-major
+    // copy of fb that batch cutouts of this output can read afterwards
+    for (int pass = 0; pass < 2; ++pass)
+      for (int32_t s = 0; s < desc->n_seg; ++s) {
+        if ((desc->seg[s].downsamp == 1) != (pass == 1)) continue;
+        RowTables &rt = row_tables(ctx, desc, freqs, s);
+        stage_row(ctx, fb, desc, rt, st);
+        launch_dedisp(ctx, rt, dmt + desc->offset[s], st);
+      }
+    if (ctx->staged_tag.fb == fb && ctx->staged_tag.D == 1) ctx->staged_tag.dmt = dmt;
   });
 }
 

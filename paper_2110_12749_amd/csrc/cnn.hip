@@ -1388,9 +1388,16 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     const dim3 ft_grid((unsigned)std::min<int64_t>((n + 7) / 8 * 8 * 16, 256 * 64));
     if (n >= kCutStageMin) {
       // a large batch: one channel-major copy of the input (in the staging
-      // buffer, which every dedispersion call restages), then contiguous reads
-      const int64_t pitch = (desc->nsamp + 4 + 255) / 256 * 256;
-      stage_raw(ctx, fb, desc->nsamp, desc->nchan, pitch, st);
+      // buffer, which every dedispersion call restages), then contiguous reads;
+      // the copy the dedispersion of this output staged last serves when it
+      // is of this filterbank at full resolution (rows at least nsamp + 4 long)
+      const auto &tag = ctx->staged_tag;
+      int64_t pitch = tag.pitch;
+      if (!(tag.fb == fb && tag.dmt == dmt && tag.D == 1 && tag.nsamp == desc->nsamp &&
+            tag.nchan == desc->nchan && tag.pitch >= desc->nsamp + 4)) {
+        pitch = (desc->nsamp + 4 + 255) / 256 * 256;
+        stage_raw(ctx, fb, desc->nsamp, desc->nchan, pitch, st);
+      }
       a.ycm = ctx->staged.as<uint8_t>();
       a.cm_pitch = pitch;
       hipLaunchKernelGGL(k_cutout_ft_cm, ft_grid, dim3(256), 0, st, a);

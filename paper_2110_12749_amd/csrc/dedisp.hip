@@ -378,6 +378,7 @@ void stage_row(gsp_ctx *ctx, const uint8_t *fb, const gsp_dmt_desc *desc, const 
                        pitch);
   }
   check_hip(hipGetLastError(), "launch staging kernel");
+  ctx->staged_tag = {fb, desc->nsamp, pitch, rt.nchan, rt.D, nullptr};
 }
 
 void stage_raw(gsp_ctx *ctx, const uint8_t *fb, int64_t nsamp, int32_t nchan, int64_t pitch, hipStream_t st) {
@@ -391,6 +392,7 @@ void stage_raw(gsp_ctx *ctx, const uint8_t *fb, int64_t nsamp, int32_t nchan, in
   auto k = mode == 2 ? k_stage<uint8_t, 2> : (mode == 1 ? k_stage<uint8_t, 1> : k_stage<uint8_t, 0>);
   hipLaunchKernelGGL(k, grid, dim3(256), 0, st, fb, nsamp, nchan, 1, nsamp, ctx->staged.as<uint8_t>(), pitch);
   check_hip(hipGetLastError(), "launch staging kernel");
+  ctx->staged_tag = {fb, nsamp, pitch, nchan, 1, nullptr};
 }
 
 template <int K, int TPW>

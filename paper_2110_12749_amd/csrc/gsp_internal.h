@@ -148,6 +148,12 @@ struct gsp_ctx {
   std::string last_error;
   std::map<std::string, std::unique_ptr<gsp::PlanCache>> plans;
   gsp::DevBuf staged;      // channel-major downsampled input of the current row
+  struct {                 // what `staged` holds: rows of fb summed over D, `pitch` apart
+    const uint8_t *fb = nullptr;
+    int64_t nsamp = 0, pitch = 0;
+    int32_t nchan = 0, D = 0;
+    const int32_t *dmt = nullptr;  // set when a gsp_dedisperse into dmt staged them last
+  } staged_tag;
   gsp::DevBuf stats;       // per-trial moments / mu / sigma
   gsp::DevBuf frags;       // search run fragments
   gsp::DevBuf counter;     // fragment counter

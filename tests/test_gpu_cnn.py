@@ -323,12 +323,19 @@ def test_cutouts_tiled_bands_high_dm(env):
     cutout_case(env, w, extra)
 
 
-@pytest.mark.parametrize("case", ["multirow", "realistic_high_dm"])
+@pytest.mark.parametrize("case", ["multirow", "realistic_high_dm", "no_full_resolution_row"])
 def test_cutouts_large_batch(env, case):
     """A batch of 300 candidates: the band sums come from a channel-major
-    copy of the input (lane per bin, unaligned dword loads).  The oracle checks
-    the search's candidates, the edge cases and every 9th random one."""
-    if case == "multirow":
+    copy of the input (lane per bin, unaligned dword loads): the copy the
+    dedispersion's full-resolution row left staged, or, in a plan without
+    such a row, one made for the cutouts.  The oracle checks the search's
+    candidates, the edge cases and every 9th random one."""
+    if case == "no_full_resolution_row":
+        segs = [(40.0, 2.0, 70, 2), (180.0, 4.0, 12, 4)]
+        w = synth.small(nchan=192, nsamp=6000, segments=segs, n_pulses=3, seed_offset=61,
+                        widths=[1, 2, 4, 8, 16, 32, 64])
+        extra = [(0, 69, 10, 16), (1, 11, 0, 3), (1, 0, 200, 33), (0, 30, 1, 2)]
+    elif case == "multirow":
         segs = [(0.0, 1.0, 40, 1), (40.0, 2.0, 70, 2), (180.0, 4.0, 12, 4)]
         w = synth.small(nchan=192, nsamp=6000, segments=segs, n_pulses=3, seed_offset=60,
                         widths=[1, 2, 4, 8, 16, 32, 64])
