@@ -723,19 +723,20 @@ __global__ __launch_bounds__(256) void k_cutout_ft(CutoutArgs a) {
 // (event, band), lane b sums bin b over the band's channels.  For a channel
 // the bins of the lanes are consecutive byte runs of its row (r D bytes
 // each), read as unaligned dwords and summed by v_sad_u8, so a wave's loads
-// are contiguous whatever the delays; no cross-lane reduction.
+// are contiguous whatever the delays; no cross-lane reduction.  The work is
+// taken band-major (every event's band group 0, then group 1, ...): the
+// copy's rows are a page or so each, and the waves in flight then read the
+// pages of a few hundred channels rather than of the whole copy, whose
+// address translations would not stay cached.
 __device__ __forceinline__ uint32_t load_u32_any(const uint8_t *p) {
   typedef uint32_t u32_unaligned __attribute__((aligned(1)));
   return *reinterpret_cast<const u32_unaligned *>(p);
 }
 __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x = blockIdx.x & 7;
-  const int64_t per_xcd = gridDim.x >> 3;
-  for (int64_t j = blockIdx.x >> 3;; j += per_xcd) {
-    const int64_t k = (j >> 4) * 8 + x;
-    if (k >= a.n) break;
-    const int band = (int)(j & 15) * 4 + wave;
+  for (int64_t j = blockIdx.x; j < a.n * 16; j += gridDim.x) {
+    const int64_t k = j % a.n;
+    const int band = (int)(j / a.n) * 4 + wave;
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
                     c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
@@ -752,13 +753,34 @@ __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
     const int64_t tb = e - (int64_t)(64 - lane) * r + 1;
     const int64_t tlo = max(tb, (int64_t)0);
     const int nb = (int)max((int64_t)0, tb + r - tlo) * D;  // raw bytes of the bin
+    // The delays of up to 64 channels are read at once (one per lane) and
+    // handed round by readlane; the loads of 16 channels go out together.
     uint32_t s = 0;
-    for (int ch = cb; ch < ce; ++ch) {
-      const uint8_t *p = a.ycm + (int64_t)ch * a.cm_pitch + (tlo + dly[ch]) * D;
-      for (int u = 0; u < nb; u += 4) {
-        uint32_t w = load_u32_any(p + u);
-        if (u + 4 > nb) w &= 0xFFFFFFFFu >> (8 * (u + 4 - nb));
-        s = __builtin_amdgcn_sad_u8(w, 0u, s);
+    for (int c0 = cb; c0 < ce; c0 += 64) {
+      const int nc = min(64, ce - c0);
+      const int dl = lane < nc ? dly[c0 + lane] : 0;
+      int i = 0;
+      for (; i + 16 <= nc; i += 16) {
+        const uint8_t *p[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          p[q] = a.ycm + (int64_t)(c0 + i + q) * a.cm_pitch + (tlo + __builtin_amdgcn_readlane(dl, i + q)) * D;
+        for (int u = 0; u < nb; u += 4) {
+          uint32_t w[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) w[q] = load_u32_any(p[q] + u);
+          const uint32_t m = u + 4 > nb ? 0xFFFFFFFFu >> (8 * (u + 4 - nb)) : 0xFFFFFFFFu;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s = __builtin_amdgcn_sad_u8(w[q] & m, 0u, s);
+        }
+      }
+      for (; i < nc; ++i) {
+        const uint8_t *p = a.ycm + (int64_t)(c0 + i) * a.cm_pitch + (tlo + __builtin_amdgcn_readlane(dl, i)) * D;
+        for (int u = 0; u < nb; u += 4) {
+          uint32_t w = load_u32_any(p + u);
+          if (u + 4 > nb) w &= 0xFFFFFFFFu >> (8 * (u + 4 - nb));
+          s = __builtin_amdgcn_sad_u8(w, 0u, s);
+        }
       }
     }
     a.ftsums[(k * 64 + band) * 64 + lane] = s;
@@ -1384,7 +1406,7 @@ int gsp_cutouts(gsp_ctx *ctx, const uint8_t *fb, const double *freqs, const int3
     ctx->ftsums.device = ctx->device;
     ctx->ftsums.reserve((size_t)n * 64 * 64 * sizeof(uint32_t));
     a.ftsums = ctx->ftsums.as<uint32_t>();
-    // a multiple of 8 workgroups (the kernels' XCD mapping needs it)
+    // a multiple of 8 workgroups (k_cutout_ft's XCD mapping needs it)
     const dim3 ft_grid((unsigned)std::min<int64_t>((n + 7) / 8 * 8 * 16, 256 * 64));
     if (n >= kCutStageMin) {
       // a large batch: one channel-major copy of the input (in the staging
