@@ -724,19 +724,22 @@ __global__ __launch_bounds__(256) void k_cutout_ft(CutoutArgs a) {
 // the bins of the lanes are consecutive byte runs of its row (r D bytes
 // each), read as unaligned dwords and summed by v_sad_u8, so a wave's loads
 // are contiguous whatever the delays; no cross-lane reduction.  The work is
-// taken band-major (every event's band group 0, then group 1, ...): the
-// copy's rows are a page or so each, and the waves in flight then read the
-// pages of a few hundred channels rather than of the whole copy, whose
-// address translations would not stay cached.
+// taken band-major (band 0 of every event, then band 1, ...; a workgroup's
+// four waves take one band of four events): the copy's rows are a page or
+// so each, and the waves in flight then read the pages of about a hundred
+// channels rather than of the whole copy, whose address translations would
+// not stay cached.
 __device__ __forceinline__ uint32_t load_u32_any(const uint8_t *p) {
   typedef uint32_t u32_unaligned __attribute__((aligned(1)));
   return *reinterpret_cast<const u32_unaligned *>(p);
 }
 __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t j = blockIdx.x; j < a.n * 16; j += gridDim.x) {
-    const int64_t k = j % a.n;
-    const int band = (int)(j / a.n) * 4 + wave;
+  const int64_t nq = (a.n + 3) / 4;  // groups of four events
+  for (int64_t j = blockIdx.x; j < nq * 64; j += gridDim.x) {
+    const int band = (int)(j / nq);
+    const int64_t k = (j % nq) * 4 + wave;
+    if (k >= a.n) continue;  // uniform over the wave; the kernel has no barrier
     const gsp_candidate c = a.cand[k];
     const bool ok = c.seg >= 0 && c.seg < a.n_seg && c.width >= 1 && c.dm_index >= 0 &&
                     c.dm_index < a.row[c.seg].n_dm && c.t_peak + c.width - 1 >= 0 &&
