@@ -206,6 +206,62 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
+// The first convolution (2 input channels, 16 outputs, 3x3, padding 1, on
+// 64 x 64 images) directly: as a GEMM it is N = 16, K = 18, a quarter of a
+// 64 x 64 tile with a gather of single elements, so one thread per output
+// pixel instead: its 18 inputs (NCHW bf16) as floats, 16 dot products of
+// exact bf16 x bf16 products summed in fp32 (the weights, [16][18] bf16 with
+// k = tap * 2 + channel, are uniform and come as scalar operands), bias,
+// ReLU, and the pixel's 16 outputs (NHWC bf16).
+__global__ __launch_bounds__(256) void k_conv1(const uint16_t *__restrict__ x, int64_t n,
+                                               const uint16_t *__restrict__ w, const float *__restrict__ bias,
+                                               uint16_t *__restrict__ act) {
+  // read-only in this kernel: through the constant address space the
+  // uniform weight loads become scalar loads (w is 4-byte aligned)
+  typedef const __attribute__((address_space(4))) uint32_t cu32;
+  cu32 *wc = (cu32 *)w;
+  const int64_t total = n * 4096;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < total; m += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t img = m >> 12;
+    const int h = (int)(m >> 6) & 63, c = (int)m & 63;
+    const uint16_t *xi = x + img * 8192;
+    float xin[18];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int hh = h + tap / 3 - 1, ww = c + tap % 3 - 1;
+      const bool in = hh >= 0 && hh < 64 && ww >= 0 && ww < 64;
+      const int hc = min(max(hh, 0), 63), wc = min(max(ww, 0), 63);  // every load in bounds, issued together
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) {
+        const float v = bf2f(xi[ch * 4096 + hc * 64 + wc]);
+        xin[tap * 2 + ch] = in ? v : 0.f;
+      }
+    }
+    // four outputs at a time (36 weight dwords in scalar registers), an
+    // 8-byte store each
+#pragma unroll 1
+    for (int o0 = 0; o0 < 16; o0 += 4) {
+      uint32_t pk[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = o0 + q;
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 18; k += 2) {
+          const uint32_t pr = wc[(o * 18 + k) >> 1];  // weights k, k + 1 (bf16, low half first)
+          acc = __builtin_fmaf(xin[k], __builtin_bit_cast(float, pr << 16), acc);
+          acc = __builtin_fmaf(xin[k + 1], __builtin_bit_cast(float, pr & 0xFFFF0000u), acc);
+        }
+        float v = acc + bias[o];
+        v = v > 0.f ? v : 0.f;
+        const uint32_t b = f2bf(v);
+        pk[q >> 1] = (q & 1) ? (pk[q >> 1] | (b << 16)) : b;
+      }
+      *reinterpret_cast<uint2 *>(act + m * 16 + o0) = make_uint2(pk[0], pk[1]);
+    }
+  }
+}
+
 __global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = 0.f;
@@ -1086,7 +1142,12 @@ void forward(gsp_cnn *c, const uint16_t *x, int64_t n, hipStream_t st, bool keep
     g.bias = p + c->L.b[l];
     g.relu = 1;
     g.out_bf16 = 1;
-    gemm(g, st);
+    if (l == 0 && sn == 2 * 64 * 64 && sc == 64 * 64 && sh == 64 && sw == 1 && cs.cin == 2 && cs.cout == 16 &&
+        H == 64 && (reinterpret_cast<uintptr_t>(wb + c->L.w[l]) & 3) == 0)
+      hipLaunchKernelGGL(k_conv1, dim3(grid_for(M)), dim3(256), 0, st, in, n, wb + c->L.w[l], p + c->L.b[l],
+                         c->act[l].as<uint16_t>());
+    else
+      gemm(g, st);
     hipLaunchKernelGGL(k_pool_fwd, dim3(grid_for(M / 4 * cs.cout)), dim3(256), 0, st, c->act[l].as<uint16_t>(),
                        (int)n, cs.cout, H, H, c->pool[l].as<uint16_t>(), c->idx[l].as<uint8_t>());
     in = c->pool[l].as<uint16_t>();
