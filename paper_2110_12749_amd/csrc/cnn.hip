@@ -828,6 +828,11 @@ __device__ __forceinline__ uint32_t load_u32_any(const uint8_t *p) {
   typedef uint32_t u32_unaligned __attribute__((aligned(1)));
   return *reinterpret_cast<const u32_unaligned *>(p);
 }
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 load_u128_any(const uint8_t *p) {
+  typedef u32x4 u32x4_unaligned __attribute__((aligned(1)));
+  return *reinterpret_cast<const u32x4_unaligned *>(p);
+}
 __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nq = (a.n + 3) / 4;  // groups of four events
@@ -846,6 +851,42 @@ __global__ __launch_bounds__(256) void k_cutout_ft_cm(CutoutArgs a) {
     const int64_t e = c.t_peak + c.width - 1;
     const int r = max(1, min(a.rmax, c.width / 8));
     const int cb = (int)((int64_t)band * nchan / 64), ce = (int)((int64_t)(band + 1) * nchan / 64);
+    const int64_t t0 = e - 64 * (int64_t)r + 1;  // first sample of bin 0
+    const int m = (r * D) >> 4;                    // 16-byte chunks per bin
+    if (t0 >= 0 && ((r * D) & 15) == 0 && (m == 1 || m == 2 || m == 4)) {
+      // Every bin after the start and a whole number of 16-byte chunks long:
+      // a channel's window (64 r D bytes from (t0 + d) D) is read as chunks,
+      // lane L taking chunks L + 64 q, so each load instruction covers 1 KiB
+      // of the row; the lane's chunk sums add up over the band's channels
+      // (the window layout is the same for every channel), and the m lanes
+      // of a bin fold theirs together once at the end.
+      uint32_t acc[4] = {0, 0, 0, 0};
+      auto add_chunks = [&](const uint8_t *p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < m) {
+            const u32x4 v = load_u128_any(p + 16 * (lane + 64 * q));
+            acc[q] = __builtin_amdgcn_sad_u8(v.x, 0u, acc[q]);
+            acc[q] = __builtin_amdgcn_sad_u8(v.y, 0u, acc[q]);
+            acc[q] = __builtin_amdgcn_sad_u8(v.z, 0u, acc[q]);
+            acc[q] = __builtin_amdgcn_sad_u8(v.w, 0u, acc[q]);
+          }
+      };
+      for (int c0 = cb; c0 < ce; c0 += 64) {
+        const int nc = min(64, ce - c0);
+        const int dl = lane < nc ? dly[c0 + lane] : 0;
+        for (int i = 0; i < nc; ++i)
+          add_chunks(a.ycm + (int64_t)(c0 + i) * a.cm_pitch + (t0 + __builtin_amdgcn_readlane(dl, i)) * D);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < m) {
+          uint32_t v = acc[q];
+          for (int sh = 1; sh < m; sh <<= 1) v += (uint32_t)__shfl_xor((int)v, sh, 64);
+          if ((lane & (m - 1)) == 0) a.ftsums[(k * 64 + band) * 64 + (lane + 64 * q) / m] = v;
+        }
+      continue;
+    }
     // bin `lane`: downsampled samples [tb, tb + r) of each channel after its
     // delay, those before the start left out (k_cutout scales the bin)
     const int64_t tb = e - (int64_t)(64 - lane) * r + 1;

@@ -326,10 +326,12 @@ def test_cutouts_tiled_bands_high_dm(env):
 @pytest.mark.parametrize("case", ["multirow", "realistic_high_dm", "no_full_resolution_row"])
 def test_cutouts_large_batch(env, case):
     """A batch of 300 candidates: the band sums come from a channel-major
-    copy of the input (lane per bin, unaligned dword loads): the copy the
-    dedispersion's full-resolution row left staged, or, in a plan without
-    such a row, one made for the cutouts.  The oracle checks the search's
-    candidates, the edge cases and every 9th random one."""
+    copy of the input: the copy the dedispersion's full-resolution row left
+    staged, or, in a plan without such a row, one made for the cutouts.
+    Bins of 16, 32 or 64 bytes wholly after the start are read as 16-byte
+    chunks of each channel's window (the wide edge cases below: r D = 16, 32
+    and 64), others one dword per lane and bin.  The oracle checks the
+    search's candidates, the edge cases and every 9th random one."""
     if case == "no_full_resolution_row":
         segs = [(40.0, 2.0, 70, 2), (180.0, 4.0, 12, 4)]
         w = synth.small(nchan=192, nsamp=6000, segments=segs, n_pulses=3, seed_offset=61,
@@ -345,7 +347,8 @@ def test_cutouts_large_batch(env, case):
         w = synth.small(nchan=4096, nsamp=90000, segments=segs, tsamp=49.152e-6, n_pulses=2, seed_offset=91,
                         widths=[1, 2, 4, 8, 16, 32, 64])
         extra = [(0, 5, 3000, 64), (0, 15, 100, 8), (1, 6, 2000, 64), (1, 0, 10, 16), (1, 11, 2300, 8),
-                 (2, 23, 0, 64), (2, 0, 1, 1)]
+                 (2, 23, 0, 64), (2, 0, 1, 1), (0, 7, 4000, 32), (2, 10, 5000, 128), (2, 4, 6000, 256),
+                 (2, 3, 8000, 512)]
     first = 12 + len(extra)  # at most: the search's top candidates + the edge cases
     cutout_case(env, w, extra, batch=300, check=list(range(first)) + list(range(first, 300, 9)))
 
